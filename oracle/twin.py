@@ -1,0 +1,94 @@
+"""NumPy brute-force twin of the C oracle, for tiny inputs only.
+
+Test infrastructure.  Written independently of ``nrr_oracle.c`` (vectorised
+NumPy over all displacements via ``sliding_window_view`` instead of plain
+loops) so that the two check each other.  Same readings of the paper:
+variance-ranked selection keeping K = floor(0.5 + N*F) blocks (ties by lower
+grid index, output in ascending grid index), exhaustive search maximising the
+Pearson-correlation reading of the NCC equation (0 for a flat block or
+window, exact ties -> smallest shift index), confidence max(0, NCC).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+
+def grid_origins(n: int, block: int, stride: int) -> np.ndarray:
+    return np.arange(0, n - block + 1, stride)
+
+
+def select(vol: np.ndarray, block: int, stride: int, fraction: float) -> np.ndarray:
+    nz, ny, nx = vol.shape
+    ox, oy, oz = (grid_origins(n, block, stride) for n in (nx, ny, nz))
+    blocks = sliding_window_view(vol, (block, block, block))[np.ix_(oz, oy, ox)]
+    blocks = blocks.reshape(len(oz) * len(oy) * len(ox), -1)
+    if vol.dtype == np.uint16:
+        v = blocks.astype(np.int64)
+        score = block ** 3 * (v * v).sum(axis=1) - v.sum(axis=1) ** 2  # exact integers
+    else:
+        score = blocks.astype(np.float64).var(axis=1)
+    n = score.shape[0]
+    k = min(n, max(0, math.floor(0.5 + n * fraction)))
+    order = np.lexsort((np.arange(n), -score))  # variance desc, grid index asc
+    chosen = np.sort(order[:k])
+    gz, rem = np.divmod(chosen, len(oy) * len(ox))
+    gy, gx = np.divmod(rem, len(ox))
+    h = (block - 1) // 2
+    return np.stack([ox[gx] + h, oy[gy] + h, oz[gz] + h], axis=1).astype(np.int32)
+
+
+def surface(ref: np.ndarray, flt: np.ndarray, center, block: int, window: int) -> np.ndarray:
+    """NCC over [-W, W]^3 indexed [dz+W, dy+W, dx+W]; NaN where invalid."""
+    h = (block - 1) // 2
+    s = 2 * window + 1
+    out = np.full((s, s, s), np.nan)
+    cx, cy, cz = (int(v) for v in center)
+    nz, ny, nx = ref.shape
+    if not (h <= cx < nx - h and h <= cy < ny - h and h <= cz < nz - h):
+        return out
+    t = ref[cz - h:cz + h + 1, cy - h:cy + h + 1, cx - h:cx + h + 1].astype(np.float64).ravel()
+    t = t - t.mean()
+    tt = float(t @ t)
+    wins = sliding_window_view(flt, (block, block, block))  # [z0, y0, x0, b, b, b]
+    rng = []
+    for c, n in ((cz, nz), (cy, ny), (cx, nx)):
+        lo = max(-window, h - c)
+        hi = min(window, n - 1 - h - c)
+        rng.append((lo, hi))
+    (lz, hz), (ly, hy), (lx, hx) = rng
+    sub = wins[cz - h + lz:cz - h + hz + 1, cy - h + ly:cy - h + hy + 1,
+               cx - h + lx:cx - h + hx + 1].astype(np.float64)
+    f = sub.reshape(sub.shape[:3] + (-1,))
+    f = f - f.mean(axis=-1, keepdims=True)
+    num = f @ t
+    ff = np.einsum("...i,...i->...", f, f)
+    den2 = tt * ff
+    val = np.where(den2 > 0, num / np.sqrt(np.where(den2 > 0, den2, 1.0)), 0.0)
+    out[lz + window:hz + window + 1, ly + window:hy + window + 1,
+        lx + window:hx + window + 1] = val
+    return out
+
+
+def match(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block: int, window: int):
+    n = len(centers)
+    disp = np.zeros((n, 3), dtype=np.int32)
+    ncc = np.zeros(n)
+    conf = np.zeros(n)
+    for k, c in enumerate(centers):
+        srf = surface(ref, flt, c, block, window)
+        flat = srf.ravel()  # C order: dz slowest, dx fastest == increasing shift index
+        if np.all(np.isnan(flat)):
+            ncc[k] = np.nan
+            continue
+        best = np.nanmax(flat)
+        i = int(np.flatnonzero(flat == best)[0])
+        dz, rem = divmod(i, (2 * window + 1) ** 2)
+        dy, dx = divmod(rem, 2 * window + 1)
+        disp[k] = (dx - window, dy - window, dz - window)
+        ncc[k] = best
+        conf[k] = max(0.0, best)
+    return disp, ncc, conf

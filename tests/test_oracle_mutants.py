@@ -1,0 +1,54 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake in a copy of ``oracle/nrr_oracle.c`` (a text
+substitution, compiled with gcc into a temporary directory, on the CPU) and
+runs the pin suite against it in a subprocess; the suite must fail.
+"""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "nrr_oracle.c")
+
+MUTANTS = {
+    "x_y_transposed": ("int64_t idx = (z * (int64_t)dims[1] + y) * (int64_t)dims[0] + x;",
+                       "int64_t idx = (z * (int64_t)dims[1] + x) * (int64_t)dims[0] + y;"),
+    "window_mean_dropped": ("double f = fbuf[i] - mean;", "double f = fbuf[i];"),
+    "shift_sign_flipped": ("double v = ncc_at(tc, a, flt, dtype, dims, b, cx - h + dx, cy - h + dy,",
+                           "double v = ncc_at(tc, a, flt, dtype, dims, b, cx - h - dx, cy - h - dy,"),
+    "tie_takes_last": ("if (v > best) {", "if (v >= best) {"),
+    "count_not_rounded": ("double k = floor(0.5 + (double)n_candidates * fraction);",
+                          "double k = floor((double)n_candidates * fraction);"),
+    "variance_ascending": ("if (a->key > b->key) return -1;\n    if (a->key < b->key) return 1;",
+                           "if (a->key > b->key) return 1;\n    if (a->key < b->key) return -1;"),
+    "flat_rule_one": ("if (!(ab > 0.0)) return 0.0;", "if (!(ab > 0.0)) return 1.0;"),
+    "sqrt_dropped": ("return xx / sqrt(ab);", "return xx / ab;"),
+    "range_too_tight": ("if (*hi > (n - 1 - h) - c) *hi = (n - 1 - h) - c;",
+                        "if (*hi > (n - 2 - h) - c) *hi = (n - 2 - h) - c;"),
+    "u16_key_unscaled": ("out_key[g] = (double)((int64_t)(b * b * b) * isq - isum * isum);",
+                         "out_key[g] = (double)(isq - isum * isum);"),
+    "block_half_size_off": ("int32_t h = (b - 1) / 2;\n    int64_t nb = (int64_t)b * b * b;\n#pragma omp parallel\n    {\n        double *tc = (double *)malloc(sizeof(double) * nb);\n        double *fb = (double *)malloc(sizeof(double) * nb);\n#pragma omp for schedule(dynamic, 1)\n        for (int64_t k = 0; k < n; ++k) {\n            int64_t cx",
+                            "int32_t h = (b - 1) / 2 + 1;\n    int64_t nb = (int64_t)b * b * b;\n#pragma omp parallel\n    {\n        double *tc = (double *)malloc(sizeof(double) * nb);\n        double *fb = (double *)malloc(sizeof(double) * nb);\n#pragma omp for schedule(dynamic, 1)\n        for (int64_t k = 0; k < n; ++k) {\n            int64_t cx"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(tmp_path, name):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) >= 1, "mutation anchor not found: %s" % name
+    mutated = src.replace(old, new, 1)
+    csrc = tmp_path / "mutant.c"
+    csrc.write_text(mutated)
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-shared", "-fPIC",
+                           "-std=c11", str(csrc), "-o", str(lib), "-lm"])
+    env = dict(os.environ, NRR_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])
