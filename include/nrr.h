@@ -1,0 +1,177 @@
+/*
+ * nrr.h -- C ABI of libnrr.so: GPU block matching for physics-based
+ * non-rigid registration (MI355X / gfx950).
+ *
+ * The library implements the data-parallel block-matching stage of the
+ * registration method ("Physics-Based Non-Rigid Registration" section of
+ * the paper): registration points are chosen where the intensity variance of
+ * the surrounding block is high (selection, "Parallel feature selection"
+ * paragraph of the HPC section), and for each point an exhaustive search
+ * over a window of integer displacements finds the displacement that
+ * maximises the normalised cross-correlation (the NCC equation) between the
+ * pre-operative block and the displaced block of the intra-operative volume
+ * (the GPU block-matching algorithm of the GPU section).
+ *
+ * Naming: `ref` is the pre-operative volume (blocks are taken from it),
+ * `flt` the intra-operative volume (the search window lies in it).  With
+ * flt(p) = ref(p - s) the displacement returned is +s.
+ *
+ * Conventions shared by every entry point:
+ *  - volumes are dense C-order [z][y][x] arrays; dims = {nx, ny, nz};
+ *  - vectors (centres, displacements) are int32 (x, y, z) triples;
+ *  - `block` is the full odd block edge b (>= 3), h = (b-1)/2; a block
+ *    centred at c covers c + o, o in [-h, h]^3;
+ *  - the search window is +-`window` voxels per axis; only displacements
+ *    whose displaced block lies fully inside the volume are evaluated;
+ *  - NCC is the Pearson correlation over the block's voxels; it is 0 when
+ *    the block or the displaced block is constant;
+ *  - among equal NCC values the displacement with the smallest shift index
+ *    ((dz+W)(2W+1) + (dy+W))(2W+1) + (dx+W) wins;
+ *  - NRR_U16 volumes hold 12-bit intensities (0..4095); NRR_F32 volumes
+ *    hold finite floats.
+ *
+ * Memory and streams: every array argument documented "device" is a device
+ * pointer owned by the caller; the library allocates no device memory and
+ * keeps no reference after returning.  Work is enqueued on `stream` (a
+ * hipStream_t passed as void*, NULL = the default stream) and the call
+ * returns without synchronising; outputs are valid after the caller
+ * synchronises the stream, and inputs/workspace must stay alive until then.
+ * Calls on different streams with different workspaces may run concurrently.
+ *
+ * Errors: every entry point returns an nrr_status and never aborts.  Host-
+ * checkable argument errors are reported synchronously and nothing is
+ * enqueued; nrr_last_error() then holds a thread-local message.
+ */
+#ifndef NRR_H
+#define NRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NRR_OK = 0,
+    NRR_ERR_INVALID_ARG = 1,      /* bad size, null pointer, out-of-range parameter */
+    NRR_ERR_BUFFER_TOO_SMALL = 2, /* output capacity or workspace too small */
+    NRR_ERR_HIP = 3,              /* a HIP runtime call or kernel launch failed */
+    NRR_ERR_UNSUPPORTED = 4       /* valid request outside this build's limits */
+} nrr_status;
+
+typedef enum {
+    NRR_U16 = 0, /* uint16 voxels, 12-bit values 0..4095 */
+    NRR_F32 = 1  /* float32 voxels */
+} nrr_dtype;
+
+/* ------------------------------------------------------------------ helpers
+ * Host-only: no device work, no synchronisation. */
+
+/* Candidate grid of the selection: grid[a] = floor((dims[a]-block)/stride)+1
+ * blocks per axis (origins g*stride, centres origin + h).  Errors:
+ * INVALID_ARG if block is even or < 3, stride < 1, or dims[a] < block. */
+nrr_status nrr_grid_shape(const int32_t dims[3], int32_t block, int32_t stride, int32_t grid[3]);
+
+/* Number of blocks the selection keeps: K = floor(0.5 + N * fraction) with
+ * N = grid[0]*grid[1]*grid[2] (the count rule "0.5 + NFeatures x Fs" of the
+ * parallel feature selection paragraph).  INVALID_ARG as nrr_grid_shape, or
+ * fraction outside (0, 1]. */
+nrr_status nrr_select_count(const int32_t dims[3], int32_t block, int32_t stride, double fraction,
+                            int64_t *k);
+
+/* Device workspace bytes nrr_select_blocks needs for these sizes. */
+nrr_status nrr_select_workspace_bytes(const int32_t dims[3], int32_t block, int32_t stride,
+                                      size_t *bytes);
+
+/* Device workspace bytes nrr_block_match needs (per-voxel window
+ * statistics of `flt` for this block size). */
+nrr_status nrr_match_workspace_bytes(nrr_dtype dtype, const int32_t dims[3], int32_t block,
+                                     size_t *bytes);
+
+/* NRR_OK if nrr_block_match supports this (dtype, block, window) on the
+ * current device; NRR_ERR_UNSUPPORTED otherwise (e.g. the search window does
+ * not fit in LDS), INVALID_ARG for malformed values. */
+nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window);
+
+/* ---------------------------------------------------------------- selection
+ * Variance-ranked block selection ("Parallel feature selection" paragraph:
+ * each candidate block's intensity variance is computed, the candidates are
+ * ordered by it and 0.5 + NFeatures x Fs of them are kept).
+ *
+ *  vol        device, dims[2]*dims[1]*dims[0] voxels of `dtype`.
+ *  centers    device, int32 [capacity][3]: receives the K centres (x,y,z) in
+ *             ascending linear grid index (gz*Gy+gy)*Gx+gx.
+ *  k_out      host: receives K (also when capacity is too small).
+ *  workspace  device, >= nrr_select_workspace_bytes() bytes, any content.
+ *
+ * Ranking: larger variance first; equal variance -> lower grid index first.
+ * u16 uses the exact integer key N*sum(x^2)-(sum x)^2; f32 uses the FP64
+ * two-pass variance summed in z, y, x order.
+ * Errors: INVALID_ARG (bad sizes/fraction, null pointers), BUFFER_TOO_SMALL
+ * (capacity < K with *k_out = K, or workspace too small), HIP.  K == 0 is a
+ * valid no-op. */
+nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                             int32_t block, int32_t stride, double fraction, int32_t *centers,
+                             int64_t capacity, int64_t *k_out, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* ----------------------------------------------------------------- matching
+ * Exhaustive NCC block matching (NCC equation and the GPU block-matching
+ * algorithm: every displacement of the window is evaluated and the maximum
+ * with its displacement is kept; cost b^3 x (2W+1)^3 per point).
+ *
+ *  ref, flt   device volumes of `dtype`, same dims.
+ *  centers    device, int32 [n][3] block centres (x,y,z) in `ref`.
+ *  disp       device, int32 [n][3]: best displacement (dx,dy,dz).
+ *  ncc        device, float [n]: NCC at that displacement.
+ *  conf       device, float [n]: confidence weight max(0, ncc) for the
+ *             downstream biomechanical solve (its S matrix).
+ *  workspace  device, >= nrr_match_workspace_bytes() bytes, any content.
+ *
+ * A centre whose block is not inside the volume gets disp (0,0,0),
+ * ncc NaN, conf 0; the other centres are unaffected.  Errors: INVALID_ARG,
+ * BUFFER_TOO_SMALL (workspace), UNSUPPORTED (see nrr_match_supported), HIP.
+ * n == 0 is a valid no-op. */
+nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
+                           const int32_t dims[3], const int32_t *centers, int64_t n,
+                           int32_t block, int32_t window, int32_t *disp, float *ncc, float *conf,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* The two halves of nrr_block_match, for callers that search the same
+ * intra-operative volume more than once with one block size (several block
+ * lists, windows or parameter sets):
+ *
+ * nrr_window_stats writes into `workspace` the per-voxel statistics of every
+ * b^3 block of `flt` (its sum and the reciprocal square root of its spread,
+ * the denominator terms of the NCC equation).  nrr_block_match_prepared then
+ * runs only the exhaustive search and reads that table: `workspace` must hold
+ * the table written for the same flt contents, dtype, dims and block.  Same
+ * argument rules and errors as nrr_block_match. */
+nrr_status nrr_window_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                            int32_t block, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype dtype,
+                                    const int32_t dims[3], const int32_t *centers, int64_t n,
+                                    int32_t block, int32_t window, int32_t *disp, float *ncc,
+                                    float *conf, const void *workspace, size_t workspace_bytes,
+                                    void *stream);
+
+/* ------------------------------------------------------------- diagnostics */
+
+/* Static string for a status code. */
+const char *nrr_status_string(nrr_status s);
+
+/* Thread-local detail message of the last non-OK return on this thread
+ * ("" if none).  Valid until the next call on the same thread. */
+const char *nrr_last_error(void);
+
+/* ABI version (major*10000 + minor*100 + patch). */
+int32_t nrr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NRR_H */

@@ -1,0 +1,226 @@
+"""GPU block matching for physics-based non-rigid registration (MI355X).
+
+Thin Python binding over ``libnrr.so`` (C ABI in ``include/nrr.h``): argument
+marshalling only -- every step of selection and matching runs in the HIP
+kernels of the library.  PyTorch provides device memory and the current HIP
+stream.  Importing this package does not load the library; the first compute
+call does, and raises ``NrrError`` if it is missing or no GPU is visible.
+
+    import torch, paper_2308_10868_amd as nrr
+    centers = nrr.select_blocks(ref, block=7, stride=7, fraction=0.25)
+    disp, ncc, conf = nrr.block_match(ref, flt, centers, block=7, window=10)
+
+Volumes are ``[nz, ny, nx]`` tensors (uint16 with 12-bit values, or
+float32) on a HIP device; centres and displacements are ``(x, y, z)`` int32.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "NrrError",
+    "library_path",
+    "load",
+    "grid_shape",
+    "select_count",
+    "select_workspace_bytes",
+    "match_workspace_bytes",
+    "match_supported",
+    "select_blocks",
+    "block_match",
+    "window_stats",
+    "U16",
+    "F32",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+U16, F32 = 0, 1
+_STATUS = {0: "NRR_OK", 1: "NRR_ERR_INVALID_ARG", 2: "NRR_ERR_BUFFER_TOO_SMALL", 3: "NRR_ERR_HIP",
+           4: "NRR_ERR_UNSUPPORTED"}
+_lib = None
+
+
+class NrrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+def library_path() -> str:
+    return os.environ.get("NRR_LIBRARY") or os.path.join(_HERE, "libnrr.so")
+
+
+def load():
+    """Load libnrr.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise NrrError(3, "libnrr.so not built at %s (run __graft_entry__.build())" % path)
+    lib = ctypes.CDLL(path)
+    P, I32, I64, F64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                            ctypes.c_size_t)
+    st = ctypes.c_int
+    sig = {
+        "nrr_grid_shape": (st, [P, I32, I32, P]),
+        "nrr_select_count": (st, [P, I32, I32, F64, P]),
+        "nrr_select_workspace_bytes": (st, [P, I32, I32, P]),
+        "nrr_match_workspace_bytes": (st, [ctypes.c_int, P, I32, P]),
+        "nrr_match_supported": (st, [ctypes.c_int, I32, I32]),
+        "nrr_select_blocks": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P, SZ, P]),
+        "nrr_block_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, P]),
+        "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
+        "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
+                                          P]),
+        "nrr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "nrr_last_error": (ctypes.c_char_p, []),
+        "nrr_version": (I32, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise NrrError(status, load().nrr_last_error().decode())
+
+
+def _dims3(dims) -> ctypes.Array:
+    return (ctypes.c_int32 * 3)(*[int(v) for v in dims])
+
+
+def grid_shape(dims, block: int, stride: int):
+    g = (ctypes.c_int32 * 3)()
+    _check(load().nrr_grid_shape(_dims3(dims), block, stride, g))
+    return tuple(g)
+
+
+def select_count(dims, block: int, stride: int, fraction: float) -> int:
+    k = ctypes.c_int64()
+    _check(load().nrr_select_count(_dims3(dims), block, stride, float(fraction), ctypes.byref(k)))
+    return k.value
+
+
+def select_workspace_bytes(dims, block: int, stride: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().nrr_select_workspace_bytes(_dims3(dims), block, stride, ctypes.byref(b)))
+    return b.value
+
+
+def match_workspace_bytes(dtype: int, dims, block: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().nrr_match_workspace_bytes(dtype, _dims3(dims), block, ctypes.byref(b)))
+    return b.value
+
+
+def match_supported(dtype: int, block: int, window: int) -> bool:
+    return load().nrr_match_supported(dtype, block, window) == 0
+
+
+# --------------------------------------------------------------- tensors
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _vol_info(t):
+    torch = _torch()
+    if not t.is_cuda:
+        raise NrrError(1, "volumes must be device tensors")
+    if t.dim() != 3 or not t.is_contiguous():
+        raise NrrError(1, "volumes must be contiguous [nz, ny, nx] tensors")
+    if t.dtype == torch.uint16:
+        dt = U16
+    elif t.dtype == torch.float32:
+        dt = F32
+    else:
+        raise NrrError(1, "volume dtype must be uint16 or float32, got %s" % t.dtype)
+    nz, ny, nx = t.shape
+    return dt, (nx, ny, nz)
+
+
+def _stream(t):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _workspace(nbytes: int, device, workspace):
+    torch = _torch()
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise NrrError(2, "workspace of %d bytes < %d" % (workspace.numel(), nbytes))
+        return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+def select_blocks(vol, block: int, stride: int, fraction: float, workspace=None):
+    """Variance-ranked selection: int32 [K, 3] centres (x, y, z) in ascending
+    grid index, on vol's device (asynchronous on the current stream)."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(vol)
+    k = select_count(dims, block, stride, fraction)
+    out = torch.empty((max(k, 1), 3), dtype=torch.int32, device=vol.device)
+    ws = _workspace(select_workspace_bytes(dims, block, stride), vol.device, workspace)
+    kout = ctypes.c_int64()
+    _check(lib.nrr_select_blocks(ctypes.c_void_p(vol.data_ptr()), dt, _dims3(dims), block, stride,
+                                 float(fraction), ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                 ctypes.byref(kout), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream(vol)))
+    return out[:kout.value]
+
+
+def window_stats(flt, block: int, workspace=None):
+    """Per-voxel window statistics of `flt` for this block size (the table
+    block_match(..., prepared=True) reads).  Returns the workspace tensor."""
+    lib = load()
+    dt, dims = _vol_info(flt)
+    ws = _workspace(match_workspace_bytes(dt, dims, block), flt.device, workspace)
+    _check(lib.nrr_window_stats(ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims), block,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(flt)))
+    return ws
+
+
+def block_match(ref, flt, centers, block: int, window: int, workspace=None, out=None,
+                prepared: bool = False):
+    """Exhaustive NCC search; returns (disp int32 [n,3], ncc f32 [n], conf f32 [n]).
+
+    With ``prepared=True`` the window-statistics pass is skipped and
+    ``workspace`` must be the table ``window_stats(flt, block)`` returned."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    dt2, dims2 = _vol_info(flt)
+    if dt != dt2 or dims != dims2 or ref.device != flt.device:
+        raise NrrError(1, "ref and flt must share dtype, shape and device")
+    if centers.dtype != torch.int32 or centers.dim() != 2 or centers.shape[1] != 3 \
+            or not centers.is_contiguous() or centers.device != ref.device:
+        raise NrrError(1, "centers must be a contiguous int32 [n, 3] tensor on ref's device")
+    n = centers.shape[0]
+    if out is None:
+        disp = torch.empty((n, 3), dtype=torch.int32, device=ref.device)
+        ncc = torch.empty(n, dtype=torch.float32, device=ref.device)
+        conf = torch.empty(n, dtype=torch.float32, device=ref.device)
+    else:
+        disp, ncc, conf = out
+    if n == 0:
+        return disp, ncc, conf
+    if prepared and workspace is None:
+        raise NrrError(1, "prepared=True needs the workspace window_stats() filled")
+    ws = _workspace(match_workspace_bytes(dt, dims, block), ref.device, workspace)
+    fn = lib.nrr_block_match_prepared if prepared else lib.nrr_block_match
+    _check(fn(ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()),
+                               dt, _dims3(dims), ctypes.c_void_p(centers.data_ptr()), n, block,
+                               window, ctypes.c_void_p(disp.data_ptr()),
+                               ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
+    return disp, ncc, conf

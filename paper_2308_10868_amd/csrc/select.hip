@@ -1,0 +1,311 @@
+// Variance-ranked block selection on the GPU.
+//
+// Follows the "Parallel feature selection" paragraph of the paper's HPC
+// section: every candidate block's intensity variance is computed, the
+// candidates are ranked by it and K = floor(0.5 + N * Fs) are kept.  The
+// paper sorts (variance, index) pairs per thread and merges them; here the
+// K-th largest key is found by a radix select over 64-bit keys (no sort of
+// the N candidates is needed) and the chosen blocks are written in ascending
+// grid index by an ordered two-phase compaction.  Ties (equal variance) are
+// broken by the lower grid index, so the result is deterministic.
+//
+// Keys: u16 volumes use the exact integer N*sum(x^2) - (sum x)^2 (= N^2 times
+// the variance, < 2^47 for b <= 15); f32 volumes use the FP64 two-pass
+// variance summed in z, y, x order without FMA contraction (bit pattern of a
+// non-negative double is monotone in its value).
+#include <hip/hip_runtime.h>
+
+#include "nrr_internal.h"
+
+namespace nrr {
+namespace {
+
+struct SelectState {
+    uint64_t kth;     // value of the K-th largest key
+    int64_t take_eq;  // how many candidates with key == kth are kept (lowest indices)
+};
+
+__global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restrict__ vol, int nx,
+                                                        int ny, int b, int stride, int gx, int gy,
+                                                        int64_t n, uint64_t *__restrict__ keys) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+    int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
+    uint64_t s = 0, q = 0;
+    for (int z = 0; z < b; ++z)
+        for (int y = 0; y < b; ++y) {
+            const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+            uint32_t rs = 0, rq = 0;  // row sums: <= 15 * 4095^2 < 2^32
+            for (int x = 0; x < b; ++x) {
+                uint32_t v = row[x];
+                rs += v;
+                rq += v * v;
+            }
+            s += rs;
+            q += rq;
+        }
+    uint64_t nb = (uint64_t)b * b * b;
+    keys[g] = nb * q - s * s;  // >= 0 by Cauchy-Schwarz
+}
+
+__global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
+                                                        int ny, int b, int stride, int gx, int gy,
+                                                        int64_t n, uint64_t *__restrict__ keys) {
+#pragma clang fp contract(off)
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+    int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
+    double nb = (double)b * b * b;
+    double sum = 0.0;
+    for (int z = 0; z < b; ++z)
+        for (int y = 0; y < b; ++y) {
+            const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+            for (int x = 0; x < b; ++x) sum += (double)row[x];
+        }
+    double mean = sum / nb;
+    double ss = 0.0;
+    for (int z = 0; z < b; ++z)
+        for (int y = 0; y < b; ++y) {
+            const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+            for (int x = 0; x < b; ++x) {
+                double d = (double)row[x] - mean;
+                ss += d * d;
+            }
+        }
+    double var = ss / nb;
+    keys[g] = __double_as_longlong(var);  // var >= +0: bit pattern is monotone
+}
+
+// Count `d` (< 256) into the LDS histogram; lanes of a wave holding the same
+// digit are merged first (one atomic per distinct digit per wave).
+__device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
+    bool pending = valid;
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        uint64_t pend = __ballot(pending);
+        if (pend == 0) break;
+        int leader = __ffsll((unsigned long long)pend) - 1;
+        uint32_t dl = __shfl(d, leader);
+        bool mine = pending && d == dl;
+        uint64_t grp = __ballot(mine);
+        if (lane == leader) atomicAdd(&hist[dl], (uint32_t)__popcll(grp));
+        if (mine) pending = false;
+    }
+}
+
+// Radix select of the K-th largest key (1 <= K <= n), 8 bits per pass from
+// the most significant byte; one workgroup.
+__global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
+                                                           int64_t n, int64_t k,
+                                                           SelectState *__restrict__ st) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int64_t s_need;
+    __shared__ uint64_t s_or;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s_prefix = 0;
+        s_mask = 0;
+        s_need = k;
+        s_or = 0;
+    }
+    __syncthreads();
+    // skip leading bytes that are zero in every key
+    uint64_t orv = 0;
+    for (int64_t i = tid; i < n; i += blockDim.x) orv |= keys[i];
+    for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off);
+    if ((tid & 63) == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
+    __syncthreads();
+    int top = 56;
+    while (top > 0 && ((s_or >> top) & 0xff) == 0) top -= 8;
+    for (int shift = top; shift >= 0; shift -= 8) {
+        for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        const uint64_t prefix = s_prefix, mask = s_mask;
+        const int64_t iters = (n + blockDim.x - 1) / blockDim.x;
+        for (int64_t it = 0; it < iters; ++it) {  // uniform trip count: ballots stay convergent
+            int64_t i = it * blockDim.x + tid;
+            uint64_t key = i < n ? keys[i] : 0;
+            bool valid = i < n && (key & mask) == prefix;
+            hist_add(hist, (uint32_t)((key >> shift) & 0xff), valid);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t need = s_need, cum = 0;
+            for (int d = 255; d >= 0; --d) {
+                int64_t h = hist[d];
+                if (cum + h >= need) {
+                    s_need = need - cum;
+                    s_prefix = prefix | ((uint64_t)d << shift);
+                    s_mask = mask | (0xffull << shift);
+                    break;
+                }
+                cum += h;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        // bytes below `top`+8 were all resolved; bytes above are zero in every key
+        st->kth = s_prefix;
+        st->take_eq = s_need;
+    }
+}
+
+// Per tile of kSelectTile candidates: how many keys are > kth and == kth.
+__global__ __launch_bounds__(256) void k_tile_counts(const uint64_t *__restrict__ keys, int64_t n,
+                                                     const SelectState *__restrict__ st,
+                                                     int64_t *__restrict__ tiles) {
+    __shared__ int64_t red[2][4];
+    const uint64_t kth = st->kth;
+    int64_t base = (int64_t)blockIdx.x * kSelectTile;
+    int64_t gt = 0, eq = 0;
+    for (int i = threadIdx.x; i < kSelectTile; i += blockDim.x) {
+        int64_t g = base + i;
+        if (g < n) {
+            uint64_t key = keys[g];
+            gt += key > kth;
+            eq += key == kth;
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        gt += __shfl_xor(gt, off);
+        eq += __shfl_xor(eq, off);
+    }
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = gt;
+        red[1][w] = eq;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        tiles[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+        tiles[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+}
+
+// Ordered compaction: candidate g is kept if key > kth, or key == kth and
+// fewer than take_eq equal keys precede it; its output slot is the number of
+// kept candidates before it.  Each thread owns kSelectTile/256 consecutive
+// candidates of the workgroup's tile.
+__global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ keys, int64_t n,
+                                                 const SelectState *__restrict__ st,
+                                                 const int64_t *__restrict__ tiles, int gx,
+                                                 int gy, int stride, int h, int64_t k,
+                                                 int32_t *__restrict__ centers) {
+    constexpr int PER = kSelectTile / 256;
+    __shared__ int64_t s_gt[256], s_eq[256];
+    __shared__ int64_t s_base[2];
+    const uint64_t kth = st->kth;
+    const int64_t take = st->take_eq;
+    const int tid = threadIdx.x;
+    // exclusive prefix over earlier tiles (strided partial sums, then reduce)
+    int64_t pg = 0, pe = 0;
+    for (int64_t t = tid; t < blockIdx.x; t += 256) {
+        pg += tiles[2 * t];
+        pe += tiles[2 * t + 1];
+    }
+    s_gt[tid] = pg;
+    s_eq[tid] = pe;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            s_gt[tid] += s_gt[tid + off];
+            s_eq[tid] += s_eq[tid + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        s_base[0] = s_gt[0];
+        s_base[1] = s_eq[0];
+    }
+    __syncthreads();
+    const int64_t base_gt = s_base[0], base_eq = s_base[1];
+    __syncthreads();
+    // this thread's candidates and local counts
+    const int64_t g0 = (int64_t)blockIdx.x * kSelectTile + (int64_t)tid * PER;
+    uint64_t kv[PER];
+    int64_t lg = 0, le = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int64_t g = g0 + j;
+        kv[j] = g < n ? keys[g] : 0;
+        bool ok = g < n;
+        lg += ok && kv[j] > kth;
+        le += ok && kv[j] == kth;
+    }
+    // inclusive scan over the workgroup (Hillis-Steele in LDS)
+    s_gt[tid] = lg;
+    s_eq[tid] = le;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int64_t a = tid >= off ? s_gt[tid - off] : 0;
+        int64_t e = tid >= off ? s_eq[tid - off] : 0;
+        __syncthreads();
+        s_gt[tid] += a;
+        s_eq[tid] += e;
+        __syncthreads();
+    }
+    int64_t gt_before = base_gt + s_gt[tid] - lg;
+    int64_t eq_before = base_eq + s_eq[tid] - le;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        int64_t g = g0 + j;
+        if (g >= n) break;
+        bool is_gt = kv[j] > kth, is_eq = kv[j] == kth;
+        bool keep = is_gt || (is_eq && eq_before < take);
+        const int64_t pos = gt_before + (eq_before < take ? eq_before : take);
+        if (keep && pos < k) {
+            int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+            centers[3 * pos + 0] = (int32_t)(ix * stride + h);
+            centers[3 * pos + 1] = (int32_t)(iy * stride + h);
+            centers[3 * pos + 2] = (int32_t)(iz * stride + h);
+        }
+        gt_before += is_gt;
+        eq_before += is_eq;
+    }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+SelectLayout select_layout(int64_t n_candidates) {
+    SelectLayout L;
+    L.n_tiles = (n_candidates + kSelectTile - 1) / kSelectTile;
+    L.keys_off = 0;
+    L.state_off = align_up((size_t)n_candidates * sizeof(uint64_t), 256);
+    L.tiles_off = L.state_off + 256;
+    L.total = L.tiles_off + align_up((size_t)L.n_tiles * 2 * sizeof(int64_t), 256);
+    return L;
+}
+
+hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3], int32_t block,
+                         int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
+                         void *workspace, hipStream_t stream) {
+    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    SelectLayout L = select_layout(n);
+    char *ws = static_cast<char *>(workspace);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys_off);
+    SelectState *st = reinterpret_cast<SelectState *>(ws + L.state_off);
+    int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
+    const int64_t nblk = (n + 255) / 256;
+    if (dtype == NRR_U16)
+        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)nblk), dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(vol), dims[0], dims[1], block, stride,
+                           grid[0], grid[1], n, keys);
+    else
+        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)nblk), dim3(256), 0, stream,
+                           static_cast<const float *>(vol), dims[0], dims[1], block, stride,
+                           grid[0], grid[1], n, keys);
+    hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, st);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
+                       st, tiles);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
+                       tiles, grid[0], grid[1], stride, (block - 1) / 2, k, centers);
+    return hipGetLastError();
+}
+
+}  // namespace nrr

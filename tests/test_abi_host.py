@@ -1,0 +1,135 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+symbol include/nrr.h declares, and the host-side helpers and argument
+validation behave as documented (no call here reaches a kernel launch)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2308_10868_amd as nrr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nrr.library_path()):
+        pytest.skip("libnrr.so not built")
+    return nrr.load()
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "nrr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nrr_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_strings(lib):
+    assert lib.nrr_version() == 10000
+    for s, text in [(0, b"ok"), (1, b"invalid argument"), (2, b"buffer too small"),
+                    (3, b"HIP runtime error"), (4, b"unsupported")]:
+        assert lib.nrr_status_string(s) == text
+
+
+def test_grid_and_count_closed_forms(lib):
+    import json
+
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "selection_counts.json")))
+    for case in g["cases"]:
+        assert list(nrr.grid_shape(case["dims"], case["block"], case["stride"])) == case["grid"]
+        assert nrr.select_count(case["dims"], case["block"], case["stride"], case["fraction"]) \
+            == case["k"]
+
+
+def test_count_rule_rounding(lib):
+    # N = 10 (10x1x1 grid of 3-blocks along x with stride 1 on a 12x3x3 volume)
+    dims = (12, 3, 3)
+    assert nrr.grid_shape(dims, 3, 1) == (10, 1, 1)
+    assert nrr.select_count(dims, 3, 1, 0.25) == 3   # 2.5 + 0.5 -> 3
+    assert nrr.select_count(dims, 3, 1, 0.24) == 2   # 2.4 + 0.5 -> 2
+    assert nrr.select_count(dims, 3, 1, 1.0) == 10
+    assert nrr.select_count(dims, 3, 1, 0.01) == 0   # 0.1 + 0.5 -> 0
+
+
+@pytest.mark.parametrize("block,stride,fraction,dims", [
+    (4, 1, 0.5, (10, 10, 10)),   # even block
+    (1, 1, 0.5, (10, 10, 10)),   # block < 3
+    (3, 0, 0.5, (10, 10, 10)),   # stride < 1
+    (3, 1, 0.0, (10, 10, 10)),   # fraction <= 0
+    (3, 1, 1.5, (10, 10, 10)),   # fraction > 1
+    (5, 1, 0.5, (10, 4, 10)),    # dims < block
+])
+def test_select_invalid_args(lib, block, stride, fraction, dims):
+    k = ctypes.c_int64(-1)
+    d = (ctypes.c_int32 * 3)(*dims)
+    s = lib.nrr_select_blocks(None, 0, d, block, stride, fraction, None, 1000, ctypes.byref(k),
+                              None, 0, None)
+    assert s == 1
+    assert len(lib.nrr_last_error()) > 0
+
+
+def test_select_capacity_too_small_reports_k(lib):
+    k = ctypes.c_int64(-1)
+    d = (ctypes.c_int32 * 3)(64, 64, 64)
+    s = lib.nrr_select_blocks(ctypes.c_void_p(1), 0, d, 7, 7, 0.2, ctypes.c_void_p(1), 100,
+                              ctypes.byref(k), ctypes.c_void_p(1), 1 << 30, None)
+    assert s == 2 and k.value == 146
+    assert b"capacity" in lib.nrr_last_error()
+
+
+def test_select_workspace_too_small(lib):
+    k = ctypes.c_int64(-1)
+    d = (ctypes.c_int32 * 3)(64, 64, 64)
+    s = lib.nrr_select_blocks(ctypes.c_void_p(1), 0, d, 7, 7, 0.2, ctypes.c_void_p(1), 146,
+                              ctypes.byref(k), ctypes.c_void_p(1), 16, None)
+    assert s == 2 and b"workspace" in lib.nrr_last_error()
+
+
+def test_select_k_zero_is_noop(lib):
+    k = ctypes.c_int64(-1)
+    d = (ctypes.c_int32 * 3)(12, 3, 3)
+    s = lib.nrr_select_blocks(None, 0, d, 3, 1, 0.01, None, 0, ctypes.byref(k), None, 0, None)
+    assert s == 0 and k.value == 0
+
+
+def test_match_invalid_args(lib):
+    d = (ctypes.c_int32 * 3)(32, 32, 32)
+    P = ctypes.c_void_p(1)
+    call = lambda **kw: lib.nrr_block_match(
+        kw.get("ref", P), kw.get("flt", P), kw.get("dtype", 0), kw.get("dims", d),
+        kw.get("centers", P), kw.get("n", 4), kw.get("block", 7), kw.get("window", 5), P, P, P,
+        P, kw.get("ws", 1 << 30), None)
+    assert call(block=6) == 1
+    assert call(window=-1) == 1
+    assert call(n=-1) == 1
+    assert call(dtype=7) == 1
+    assert call(centers=None) == 1
+    assert call(dims=(ctypes.c_int32 * 3)(32, 5, 32)) == 1
+    assert call(n=0, centers=None, ref=None) == 0       # n == 0: no-op
+    assert call(ws=16) == 2                              # workspace too small
+    assert call(block=17) == 4                           # not built
+
+
+def test_match_workspace_size(lib):
+    assert nrr.match_workspace_bytes(nrr.U16, (256, 256, 124), 7) >= 250 * 250 * 118 * 8
+    assert nrr.match_workspace_bytes(nrr.F32, (64, 64, 64), 7) >= 58 ** 3 * 16
+    assert lib.nrr_match_supported(0, 17, 3) == 4
+    assert lib.nrr_match_supported(0, 8, 3) == 1
+    assert lib.nrr_match_supported(0, 7, -1) == 1
+
+
+def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setenv("NRR_LIBRARY", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(nrr, "_lib", None)
+    with pytest.raises(nrr.NrrError):
+        nrr.load()
