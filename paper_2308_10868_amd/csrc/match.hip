@@ -151,6 +151,66 @@ __device__ inline void write_result(const Params &p, int64_t blk, int dx, int dy
     p.conf[blk] = v > 0.0f ? v : 0.0f;
 }
 
+// Stage a box of a volume into LDS rows: row r = z*py + y (z < pz, y < py) of
+// `pitch` elements (pitch a multiple of 4).  Element (z, y, x) becomes
+// conv(v) for v = src at (z0+z, y0+y, x0+x) when z < ez, y < ey and x < ex,
+// and 0 elsewhere (tile padding is never read as a real voxel).  Each lane
+// moves chunks of 4 consecutive x; UNR chunks per lane are loaded before any
+// is written so several global loads are in flight, and the chunk coordinates
+// advance incrementally (no integer division in the loop).
+template <typename Src, typename Dst, typename Conv>
+__device__ inline void stage_box(const Src *__restrict__ src, int nx, int ny, int x0, int y0,
+                                 int z0, int ex, int ey, int ez, Dst *__restrict__ dst, int pitch,
+                                 int py, int pz, Conv conv) {
+    constexpr int UNR = 8;
+    const int cpr = pitch >> 2;
+    const int total = pz * py * cpr;
+    const int drow = NT / cpr, dxc = NT - drow * cpr;
+    int row = (int)threadIdx.x / cpr;
+    int xc = (int)threadIdx.x - row * cpr;
+    int z = row / py, y = row - z * py;
+    for (int c0 = 0; c0 < total; c0 += NT * UNR) {
+        Src v[UNR][4];
+        int off[UNR], xs[UNR];
+        bool rin[UNR], live[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            live[u] = c0 + u * NT + (int)threadIdx.x < total;
+            xs[u] = 4 * xc;
+            off[u] = (z * py + y) * pitch + 4 * xc;
+            rin[u] = live[u] && z < ez && y < ey;
+            const Src *s = src + ((int64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + 4 * xc);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[u][e] = (rin[u] && 4 * xc + e < ex) ? s[e] : Src(0);
+            xc += dxc;
+            y += drow;
+            if (xc >= cpr) {
+                xc -= cpr;
+                ++y;
+            }
+            while (y >= py) {
+                y -= py;
+                ++z;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (!live[u]) continue;
+            Dst o[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[e] = (rin[u] && xs[u] + e < ex) ? conv(v[u][e]) : Dst(0);
+            if constexpr (sizeof(Dst) == 2) {
+                uint2 w;
+                w.x = (uint32_t)(uint16_t)o[0] | ((uint32_t)(uint16_t)o[1] << 16);
+                w.y = (uint32_t)(uint16_t)o[2] | ((uint32_t)(uint16_t)o[3] << 16);
+                *reinterpret_cast<uint2 *>(dst + off[u]) = w;
+            } else {
+                *reinterpret_cast<float4 *>(dst + off[u]) = make_float4(o[0], o[1], o[2], o[3]);
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------- 12-bit volumes
 
 // Shape of the staged window for a block: x/y padded to whole tiles, one
@@ -189,7 +249,8 @@ __global__ __launch_bounds__(NT) void k_match_u16(Params p) {
     const uint16_t *ref = static_cast<const uint16_t *>(p.ref);
     const uint16_t *flt = static_cast<const uint16_t *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
-    const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1, PZ = g.dz + B;
+    // row pitch rounded to 4 elements (8-byte LDS writes)
+    const int PX = (txn * RX + B - 1 + 3) & ~3, PY = tyn * RY + B - 1, PZ = g.dz + B;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1, ez = g.dz + B - 1;  // real window extent
 
     // ---- stage T' = T - 2048 as (plane 2m, plane 2m+1) pairs, zero padded
@@ -206,18 +267,8 @@ __global__ __launch_bounds__(NT) void k_match_u16(Params p) {
         red[1] += v * v;
     }
     // ---- stage the window F' = F - 2048 (zero outside the real window)
-    {
-        const int rows = PZ * PY;
-        const int wv = tid >> 6, lane = tid & 63;
-        for (int r = wv; r < rows; r += NT / 64) {
-            const int z = r / PY, y = r % PY;
-            const bool rin = z < ez && y < ey;
-            const uint16_t *src = flt + ((int64_t)(g.wz0 + z) * p.ny + (g.wy0 + y)) * p.nx + g.wx0;
-            int16_t *dst = win + (int64_t)r * PX;
-            for (int x = lane; x < PX; x += 64)
-                dst[x] = (rin && x < ex) ? (int16_t)((int)src[x] - 2048) : (int16_t)0;
-        }
-    }
+    stage_box(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0, ex, ey, ez, win, PX, PY, PZ,
+              [](uint16_t v) { return (int16_t)((int)v - 2048); });
     wg_sum<long long, 2>(red, s_red);  // includes the barrier that publishes LDS
     const long long sT = red[0];
     const long long varT = (long long)N * red[1] - sT * sT;
@@ -379,7 +430,7 @@ __global__ __launch_bounds__(NT) void k_match_f32(Params p) {
     const float *ref = static_cast<const float *>(p.ref);
     const float *flt = static_cast<const float *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
-    const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1, PZ = g.dz + B - 1;
+    const int PX = (txn * RX + B - 1 + 3) & ~3, PY = tyn * RY + B - 1, PZ = g.dz + B - 1;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1;
 
     auto tval = [&](int o) {
@@ -404,17 +455,8 @@ __global__ __launch_bounds__(NT) void k_match_f32(Params p) {
         }
         tf[i] = v;
     }
-    {
-        const int rows = PZ * PY;
-        const int wv = tid >> 6, lane = tid & 63;
-        for (int r = wv; r < rows; r += NT / 64) {
-            const int z = r / PY, y = r % PY;
-            const bool rin = y < ey;
-            const float *src = flt + ((int64_t)(g.wz0 + z) * p.ny + (g.wy0 + y)) * p.nx + g.wx0;
-            float *dst = win + (int64_t)r * PX;
-            for (int x = lane; x < PX; x += 64) dst[x] = (rin && x < ex) ? src[x] - c : 0.0f;
-        }
-    }
+    stage_box(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0, ex, ey, PZ, win, PX, PY, PZ,
+              [c](float v) { return v - c; });
     wg_sum<double, 2>(r2, s_red);
     const double sT = r2[0];
     if (!(r2[1] > 0.0)) {  // flat block
@@ -535,7 +577,7 @@ const Variant kVariants[] = {
 
 size_t lds_bytes(nrr_dtype dtype, int b, int rx, int ry, int w) {
     const int d = 2 * w + 1;
-    const int px = (d + rx - 1) / rx * rx + b - 1, py = (d + ry - 1) / ry * ry + b - 1;
+    const int px = ((d + rx - 1) / rx * rx + b - 1 + 3) & ~3, py = (d + ry - 1) / ry * ry + b - 1;
     const int bp = (b + 3) & ~3;
     if (dtype == NRR_U16) {
         const int pz = d + b;

@@ -25,28 +25,34 @@ struct SelectState {
     int64_t take_eq;  // how many candidates with key == kth are kept (lowest indices)
 };
 
+// One wavefront per candidate block: lanes take the block's b*b rows, sum
+// them exactly in integers and reduce across the wavefront.
 __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restrict__ vol, int nx,
                                                         int ny, int b, int stride, int gx, int gy,
                                                         int64_t n, uint64_t *__restrict__ keys) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
-    int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= n) return;  // whole wavefront leaves together
+    const int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+    const int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
     uint64_t s = 0, q = 0;
-    for (int z = 0; z < b; ++z)
-        for (int y = 0; y < b; ++y) {
-            const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            uint32_t rs = 0, rq = 0;  // row sums: <= 15 * 4095^2 < 2^32
-            for (int x = 0; x < b; ++x) {
-                uint32_t v = row[x];
-                rs += v;
-                rq += v * v;
-            }
-            s += rs;
-            q += rq;
+    for (int r = lane; r < b * b; r += 64) {
+        const int z = r / b, y = r - z * b;
+        const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+        uint32_t rs = 0, rq = 0;  // row sums: <= 15 * 4095^2 < 2^32
+        for (int x = 0; x < b; ++x) {
+            const uint32_t v = row[x];
+            rs += v;
+            rq += v * v;
         }
-    uint64_t nb = (uint64_t)b * b * b;
-    keys[g] = nb * q - s * s;  // >= 0 by Cauchy-Schwarz
+        s += rs;
+        q += rq;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        q += __shfl_xor(q, off);
+    }
+    if (lane == 0) keys[g] = (uint64_t)b * b * b * q - s * s;  // >= 0 by Cauchy-Schwarz
 }
 
 __global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
@@ -78,20 +84,19 @@ __global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict_
     keys[g] = __double_as_longlong(var);  // var >= +0: bit pattern is monotone
 }
 
-// Count `d` (< 256) into the LDS histogram; lanes of a wave holding the same
-// digit are merged first (one atomic per distinct digit per wave).
+// Count `d` (< 256) into the LDS histogram.  A wavefront whose counted lanes
+// all hold the same digit (common in the leading bytes) adds once; otherwise
+// every lane adds its own (LDS atomics on distinct bins proceed in parallel).
 __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
-    bool pending = valid;
-    const int lane = threadIdx.x & 63;
-    while (true) {
-        uint64_t pend = __ballot(pending);
-        if (pend == 0) break;
-        int leader = __ffsll((unsigned long long)pend) - 1;
-        uint32_t dl = __shfl(d, leader);
-        bool mine = pending && d == dl;
-        uint64_t grp = __ballot(mine);
-        if (lane == leader) atomicAdd(&hist[dl], (uint32_t)__popcll(grp));
-        if (mine) pending = false;
+    const uint64_t act = __ballot(valid);
+    if (act == 0) return;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const uint32_t dl = __shfl(d, leader);
+    const uint64_t same = __ballot(valid && d == dl);
+    if (same == act) {
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&hist[dl], (uint32_t)__popcll(act));
+    } else if (valid) {
+        atomicAdd(&hist[d], 1u);
     }
 }
 
@@ -132,17 +137,36 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
             hist_add(hist, (uint32_t)((key >> shift) & 0xff), valid);
         }
         __syncthreads();
-        if (tid == 0) {
-            int64_t need = s_need, cum = 0;
-            for (int d = 255; d >= 0; --d) {
-                int64_t h = hist[d];
-                if (cum + h >= need) {
-                    s_need = need - cum;
-                    s_prefix = prefix | ((uint64_t)d << shift);
-                    s_mask = mask | (0xffull << shift);
-                    break;
+        if (tid < 64) {  // wavefront 0: find the digit holding the need-th largest key
+            // lane l owns bins 255-4l .. 252-4l (descending)
+            uint32_t h4[4];
+            uint32_t mine = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h4[j] = hist[255 - 4 * tid - j];
+                mine += h4[j];
+            }
+            // exclusive prefix over lower lanes = count of keys in higher bins
+            uint32_t incl = mine;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = __shfl_up(incl, off);
+                if (tid >= off) incl += o;
+            }
+            const int64_t need = s_need;
+            const int64_t above = (int64_t)(incl - mine);
+            if (above < need && need <= (int64_t)incl) {
+                int64_t cum = above;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (cum + h4[j] >= need) {
+                        const int d = 255 - 4 * tid - j;
+                        s_need = need - cum;
+                        s_prefix = prefix | ((uint64_t)d << shift);
+                        s_mask = mask | (0xffull << shift);
+                        break;
+                    }
+                    cum += h4[j];
                 }
-                cum += h;
             }
         }
         __syncthreads();
@@ -293,7 +317,7 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
     int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
     const int64_t nblk = (n + 255) / 256;
     if (dtype == NRR_U16)
-        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)nblk), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
                            static_cast<const uint16_t *>(vol), dims[0], dims[1], block, stride,
                            grid[0], grid[1], n, keys);
     else
