@@ -204,8 +204,7 @@ nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const in
     a.n = n;
     a.block = block;
     a.window = window;
-    a.stat_s = static_cast<const char *>(workspace) + L.s_off;
-    a.stat_r = static_cast<const char *>(workspace) + L.r_off;
+    a.stats = workspace;
     a.ox = L.ox;
     a.oy = L.oy;
     a.disp = disp;

@@ -1,30 +1,33 @@
 // Exhaustive NCC block matching on gfx950.
 //
 // The paper's GPU algorithm (GPU section) maps one image block to one thread
-// block and spreads the loop over the candidate displacements of the search
-// window across the threads, then takes the maximum similarity and its
+// block, spreads the loop over the candidate displacements of the search
+// window across the threads, and then takes the maximum similarity and its
 // displacement.  This kernel keeps that outer mapping (one workgroup per
 // selected block) and re-designs the inner part for CDNA:
 //
-//  * the block's whole search window of `flt` is staged once in LDS (every
-//    voxel is then reused by all displacements that touch it), and the
-//    pre-operative block T is staged beside it;
+//  * the block's search window of `flt` is staged in LDS, a run of CZ
+//    displacement planes at a time (z-chunks, so any window size fits), and
+//    the pre-operative block T is staged beside it; every staged voxel is
+//    then reused by all displacements that touch it;
 //  * each thread owns an RX x RY tile of (dx, dy) displacements at one dz and
-//    keeps RX*RY accumulators in registers; a window row loaded from LDS is
-//    reused by every (tile displacement, block column) pair that reads it;
-//  * 12-bit data: the cross term sum T'F' (T' = T-2048, F' = F-2048) is
-//    accumulated exactly in int32 with v_dot2_i32_i16, two voxels (planes z
-//    and z+1) per instruction; the block's planes are grouped so that no
-//    int32 partial sum can overflow (|T'|,|F'| <= 2048);
-//  * float data: the cross term sum T^(F - c) with T^ = T - mean(T) and
-//    c = mean(T) is accumulated in FP32 FMA;
-//  * the window statistics (sum F and 1/sqrt of the spread) come from a
+//    keeps RX*RY accumulators in registers; a window row read from LDS is
+//    reused by every (tile displacement, block column) pair that needs it;
+//    LDS is read as single aligned dwords (4 bytes per staged element);
+//  * two arithmetic forms of the cross term sum_o T(o) F(o+d):
+//      DOT2 (12-bit data, exact): T' = T-2048 and F' = F-2048 as int16
+//        pairs of planes (z, z+1), multiplied and accumulated exactly in int32
+//        by v_dot2_i32_i16; the block's planes are grouped so no int32 partial
+//        sum can overflow (|T'|, |F'| <= 2048);
+//      FMA (any data): T^ = T - mean(T) in FP32 against F - c (c = the
+//        block mean, rounded to an integer for 12-bit data) with v_fmac_f32;
+//  * the window statistics (sum F and 1/sqrt of its spread) come from a
 //    per-voxel table computed once per call (stats.hip), so the epilogue per
 //    displacement is a handful of operations;
-//  * displacements are ranked by key = cov * rsqrt(varF), which is
-//    proportional to the NCC (the block's own spread is a constant factor);
-//    the argmax keeps the smallest shift index among equal keys and is
-//    reduced across the workgroup with wavefront shuffles;
+//  * displacements are ranked by key = cov * rsqrt(varF), proportional to the
+//    NCC (the block's own spread is a constant factor); the argmax keeps the
+//    smallest shift index among equal keys and is reduced across the
+//    workgroup with wavefront shuffles;
 //  * the NCC reported for the winning displacement is recomputed exactly
 //    (integer sums for 12-bit data, two-pass FP64 for float data) from the
 //    volumes, so it does not inherit the ranking arithmetic's rounding.
@@ -32,6 +35,10 @@
 
 #include <climits>
 #include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <type_traits>
 
 #include "nrr_internal.h"
 
@@ -39,9 +46,14 @@ namespace nrr {
 namespace {
 
 typedef short short2v __attribute__((ext_vector_type(2)));
+// LDS dword read one at a time: the volatile qualifier keeps the compiler from
+// merging neighbouring window reads into wider, misaligned LDS accesses, and
+// the LDS address space keeps them ds_read_b32 with immediate offsets.
+typedef __attribute__((address_space(3))) const volatile uint32_t lds_word;
 
-constexpr int NT = 256;     // threads per workgroup (4 wavefronts)
-constexpr int MAX_B = 15;   // largest block edge served
+constexpr int MAX_B = 15;  // largest block edge served
+constexpr int ZPAD = 1;    // padding dwords after each staged window plane
+enum Arith { DOT2 = 0, FMA = 1 };
 
 struct Params {
     const void *ref;
@@ -51,8 +63,8 @@ struct Params {
     int64_t n;
     int64_t first;  // first block of this launch
     int w;
-    const void *stat_s;
-    const void *stat_r;
+    int cz;  // displacement planes per z-chunk
+    const void *stats;  // StatU16 / StatF32 records over block origins
     int ox, oy;
     int32_t *disp;
     float *ncc;
@@ -104,7 +116,7 @@ __device__ inline void better(K &bk, int &bi, K k, int i) {
 }
 
 // Workgroup argmax of (key, shift index): largest key, smallest index on ties.
-template <typename K>
+template <int NT, typename K>
 __device__ inline void wg_argmax(K &key, int &idx, K *s_key, int *s_idx) {
     for (int off = 32; off > 0; off >>= 1) {
         K ok = __shfl_xor(key, off);
@@ -123,7 +135,7 @@ __device__ inline void wg_argmax(K &key, int &idx, K *s_key, int *s_idx) {
     __syncthreads();
 }
 
-template <typename T, int NV>
+template <int NT, typename T, int NV>
 __device__ inline void wg_sum(T (&v)[NV], T *s_red) {
 #pragma unroll
     for (int k = 0; k < NV; ++k)
@@ -151,37 +163,44 @@ __device__ inline void write_result(const Params &p, int64_t blk, int dx, int dy
     p.conf[blk] = v > 0.0f ? v : 0.0f;
 }
 
-// Stage a box of a volume into LDS rows: row r = z*py + y (z < pz, y < py) of
-// `pitch` elements (pitch a multiple of 4).  Element (z, y, x) becomes
-// conv(v) for v = src at (z0+z, y0+y, x0+x) when z < ez, y < ey and x < ex,
-// and 0 elsewhere (tile padding is never read as a real voxel).  Each lane
-// moves chunks of 4 consecutive x; UNR chunks per lane are loaded before any
-// is written so several global loads are in flight, and the chunk coordinates
-// advance incrementally (no integer division in the loop).
-template <typename Src, typename Dst, typename Conv>
-__device__ inline void stage_box(const Src *__restrict__ src, int nx, int ny, int x0, int y0,
-                                 int z0, int ex, int ey, int ez, Dst *__restrict__ dst, int pitch,
-                                 int py, int pz, Conv conv) {
-    constexpr int UNR = 8;
-    const int cpr = pitch >> 2;
+// Stage planes [z0, z0 + pz) of the window into LDS as 4-byte elements at
+// z*plane + y*pitch + x (plane >= py*pitch); element (z, y, x) = make(a, b, nb)
+// where a = src(z0+z, y0+y, x0+x) and, with PAIR, b = the same voxel of the
+// next plane (nb = false and b = 0 past plane `ez`), for y < ey and x < ex;
+// 0 elsewhere (tile padding).  Each lane moves chunks of 4 consecutive x;
+// UNR chunks per lane are loaded before any is written so several global
+// loads are in flight, and the chunk coordinates advance incrementally (no
+// integer division in the loop).
+template <int NT, bool PAIR, typename Src, typename Make>
+__device__ inline void stage_planes(const Src *__restrict__ src, int nx, int ny, int x0, int y0,
+                                    int z0, int ex, int ey, int ez, uint32_t *__restrict__ dst,
+                                    int pitch, int plane, int py, int pz, Make make) {
+    constexpr int UNR = 4;
+    const int cpr = (pitch + 3) >> 2;  // chunks per row
     const int total = pz * py * cpr;
     const int drow = NT / cpr, dxc = NT - drow * cpr;
     int row = (int)threadIdx.x / cpr;
     int xc = (int)threadIdx.x - row * cpr;
     int z = row / py, y = row - z * py;
     for (int c0 = 0; c0 < total; c0 += NT * UNR) {
-        Src v[UNR][4];
-        int off[UNR], xs[UNR];
-        bool rin[UNR], live[UNR];
+        Src a[UNR][4], b[UNR][4];
+        int base[UNR], xs[UNR];
+        bool rin[UNR], nin[UNR], live[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             live[u] = c0 + u * NT + (int)threadIdx.x < total;
             xs[u] = 4 * xc;
-            off[u] = (z * py + y) * pitch + 4 * xc;
-            rin[u] = live[u] && z < ez && y < ey;
+            base[u] = z * plane + y * pitch + 4 * xc;
+            rin[u] = live[u] && y < ey && z < ez;
+            nin[u] = PAIR && rin[u] && z + 1 < ez;
             const Src *s = src + ((int64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + 4 * xc);
+            const Src *s1 = s + (int64_t)ny * nx;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[u][e] = (rin[u] && 4 * xc + e < ex) ? s[e] : Src(0);
+            for (int e = 0; e < 4; ++e) {
+                const bool in = 4 * xc + e < ex;
+                a[u][e] = (rin[u] && in) ? s[e] : Src(0);
+                b[u][e] = (PAIR && nin[u] && in) ? s1[e] : Src(0);
+            }
             xc += dxc;
             y += drow;
             if (xc >= cpr) {
@@ -196,48 +215,44 @@ __device__ inline void stage_box(const Src *__restrict__ src, int nx, int ny, in
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             if (!live[u]) continue;
-            Dst o[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) o[e] = (rin[u] && xs[u] + e < ex) ? conv(v[u][e]) : Dst(0);
-            if constexpr (sizeof(Dst) == 2) {
-                uint2 w;
-                w.x = (uint32_t)(uint16_t)o[0] | ((uint32_t)(uint16_t)o[1] << 16);
-                w.y = (uint32_t)(uint16_t)o[2] | ((uint32_t)(uint16_t)o[3] << 16);
-                *reinterpret_cast<uint2 *>(dst + off[u]) = w;
-            } else {
-                *reinterpret_cast<float4 *>(dst + off[u]) = make_float4(o[0], o[1], o[2], o[3]);
+            for (int e = 0; e < 4; ++e) {
+                const int x = xs[u] + e;
+                if (x < pitch) {
+                    const bool in = rin[u] && x < ex;
+                    dst[base[u] + e] = in ? make(a[u][e], b[u][e], nin[u]) : 0u;
+                }
             }
         }
     }
 }
 
-// --------------------------------------------------------- 12-bit volumes
-
-// Shape of the staged window for a block: x/y padded to whole tiles, one
-// extra z plane for the zero half of the last plane pair when b is odd.
-template <int B, int RX, int RY>
-struct U16Shape {
-    static constexpr int P = (B + 1) / 2;       // plane pairs of the block
-    static constexpr int BP = (B + 3) & ~3;     // padded row of T pairs (dwords)
-    static constexpr int TP_DWORDS = P * B * BP;
-    // exact int32 groups: a plane contributes at most B*B*2048*2048
+// Exact int32 grouping for DOT2: a plane contributes at most B*B*2048*2048.
+template <int B>
+struct Groups {
+    static constexpr int P = (B + 1) / 2;  // plane pairs of the block
     static constexpr long long PLANE_MAX = (long long)B * B * 2048 * 2048;
     static constexpr int GPAIRS = (int)(2147483647LL / PLANE_MAX) / 2;  // pairs per group
     static constexpr int NG = (P + GPAIRS - 1) / GPAIRS;
     static_assert(GPAIRS >= 1, "block edge too large for exact int32 groups");
 };
 
-template <int B, int RX, int RY>
-__global__ __launch_bounds__(NT) void k_match_u16(Params p) {
-    using S = U16Shape<B, RX, RY>;
-    constexpr int H = (B - 1) / 2, P = S::P, BP = S::BP, N = B * B * B;
-    constexpr int GP = S::GPAIRS, NG = S::NG;
+template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
+__global__ __launch_bounds__(NT) void k_match(Params p) {
+    constexpr bool U16 = sizeof(Vox) == 2;
+    static_assert(ARITH == FMA || U16, "DOT2 needs 12-bit data");
+    constexpr int H = (B - 1) / 2, N = B * B * B, BP = (B + 3) & ~3;
+    constexpr int P = Groups<B>::P, GP = Groups<B>::GPAIRS, NG = Groups<B>::NG;
+    constexpr int TPL = ARITH == DOT2 ? P : B;  // block planes (pairs) in the T table
+    constexpr int TP_WORDS = TPL * B * BP;
+    using KeyT = typename std::conditional<U16, float, double>::type;
     extern __shared__ __align__(16) unsigned char lds[];
-    int32_t *tp = reinterpret_cast<int32_t *>(lds);                 // [P][B][BP] pairs
-    int16_t *win = reinterpret_cast<int16_t *>(lds + S::TP_DWORDS * 4);  // [PZ][PY][PX]
-    __shared__ float s_key[NT / 64];
+    uint32_t *tp = reinterpret_cast<uint32_t *>(lds);                  // [TPL][B][BP]
+    uint32_t *win = reinterpret_cast<uint32_t *>(lds + TP_WORDS * 4);  // [cz+B-1][PY][PX]
+    __shared__ KeyT s_key[NT / 64];
     __shared__ int s_idx[NT / 64];
     __shared__ long long s_red[(NT / 64) * 5];
+    __shared__ double s_redd[(NT / 64) * 3];
 
     const int64_t blk = p.first + xcd_block(blockIdx.x, gridDim.x);
     const Geom g = make_geom(p, blk, H);
@@ -246,311 +261,336 @@ __global__ __launch_bounds__(NT) void k_match_u16(Params p) {
         if (tid == 0) write_result(p, blk, 0, 0, 0, NAN);
         return;
     }
-    const uint16_t *ref = static_cast<const uint16_t *>(p.ref);
-    const uint16_t *flt = static_cast<const uint16_t *>(p.flt);
+    const Vox *ref = static_cast<const Vox *>(p.ref);
+    const Vox *flt = static_cast<const Vox *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
-    // row pitch rounded to 4 elements (8-byte LDS writes)
-    const int PX = (txn * RX + B - 1 + 3) & ~3, PY = tyn * RY + B - 1, PZ = g.dz + B;
-    const int ex = g.dx + B - 1, ey = g.dy + B - 1, ez = g.dz + B - 1;  // real window extent
-
-    // ---- stage T' = T - 2048 as (plane 2m, plane 2m+1) pairs, zero padded
-    for (int i = tid; i < S::TP_DWORDS; i += NT) tp[i] = 0;
-    __syncthreads();
-    int16_t *tp16 = reinterpret_cast<int16_t *>(tp);
-    long long red[2] = {0, 0};  // sum T', sum T'^2
-    for (int o = tid; o < N; o += NT) {
-        const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        const int v = (int)ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx +
-                               (g.cx - H + ox)] - 2048;
-        tp16[2 * (((oz >> 1) * B + oy) * BP + ox) + (oz & 1)] = (int16_t)v;
-        red[0] += v;
-        red[1] += v * v;
-    }
-    // ---- stage the window F' = F - 2048 (zero outside the real window)
-    stage_box(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0, ex, ey, ez, win, PX, PY, PZ,
-              [](uint16_t v) { return (int16_t)((int)v - 2048); });
-    wg_sum<long long, 2>(red, s_red);  // includes the barrier that publishes LDS
-    const long long sT = red[0];
-    const long long varT = (long long)N * red[1] - sT * sT;
-    if (varT == 0) {  // flat block: every NCC is 0, the smallest shift index wins
-        if (tid == 0) write_result(p, blk, g.lox, g.loy, g.loz, 0.0f);
-        return;
-    }
-
-    // ---- exhaustive search over this workgroup's displacement tiles
-    const int32_t *stat_s = static_cast<const int32_t *>(p.stat_s);
-    const float *stat_r = static_cast<const float *>(p.stat_r);
-    const double dN = (double)N, dST = (double)sT;
-    const int side = 2 * p.w + 1;
-    float bk = -INFINITY;
-    int bi = INT_MAX;
-    const int ntiles = txn * tyn * g.dz;
-    const int plane = PY * PX;
-    for (int t = tid; t < ntiles; t += NT) {
-        const int tx = t % txn, ty = (t / txn) % tyn, dz = t / (txn * tyn);
-        int acc[RX][RY];
-        int acc0[RX][RY];
-        double dacc[NG > 2 ? RX : 1][NG > 2 ? RY : 1];
-#pragma unroll
-        for (int i = 0; i < RX; ++i)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                acc[i][j] = 0;
-                acc0[i][j] = 0;
-                if constexpr (NG > 2) dacc[i][j] = 0.0;
-            }
-        const int16_t *base = win + (dz * PY + ty * RY) * PX + tx * RX;
-        for (int m = 0; m < P; ++m) {
-            int tq[B][B];
-            const int32_t *tpm = tp + m * B * BP;
-#pragma unroll
-            for (int oy = 0; oy < B; ++oy)
-#pragma unroll
-                for (int ox = 0; ox < B; ++ox) tq[oy][ox] = tpm[oy * BP + ox];
-            const int16_t *w0 = base + 2 * m * plane;
-            const int16_t *w1 = w0 + plane;
-#pragma unroll
-            for (int yw = 0; yw < RY + B - 1; ++yw) {
-                short2v f[RX + B - 1];
-#pragma unroll
-                for (int xw = 0; xw < RX + B - 1; ++xw) {
-                    f[xw].x = w0[yw * PX + xw];
-                    f[xw].y = w1[yw * PX + xw];
-                }
-#pragma unroll
-                for (int j = 0; j < RY; ++j) {
-                    const int oy = yw - j;
-                    if (oy < 0 || oy >= B) continue;
-#pragma unroll
-                    for (int i = 0; i < RX; ++i)
-#pragma unroll
-                        for (int ox = 0; ox < B; ++ox)
-                            acc[i][j] = __builtin_amdgcn_sdot2(
-                                f[i + ox], __builtin_bit_cast(short2v, tq[oy][ox]), acc[i][j],
-                                false);
-                }
-            }
-            if constexpr (NG == 2) {
-                if (m == GP - 1) {
-#pragma unroll
-                    for (int i = 0; i < RX; ++i)
-#pragma unroll
-                        for (int j = 0; j < RY; ++j) {
-                            acc0[i][j] = acc[i][j];
-                            acc[i][j] = 0;
-                        }
-                }
-            } else if constexpr (NG > 2) {
-                if ((m + 1) % GP == 0) {
-#pragma unroll
-                    for (int i = 0; i < RX; ++i)
-#pragma unroll
-                        for (int j = 0; j < RY; ++j) {
-                            dacc[i][j] += (double)acc[i][j];
-                            acc[i][j] = 0;
-                        }
-                }
-            }
-        }
-        // ---- rank this tile's displacements
-#pragma unroll
-        for (int i = 0; i < RX; ++i)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                const int xx = tx * RX + i, yy = ty * RY + j;
-                if (xx < g.dx && yy < g.dy) {
-                    const int64_t o = ((int64_t)(g.wz0 + dz) * p.oy + (g.wy0 + yy)) * p.ox +
-                                      (g.wx0 + xx);
-                    double x;
-                    if constexpr (NG == 1)
-                        x = (double)acc[i][j];
-                    else if constexpr (NG == 2)
-                        x = (double)acc0[i][j] + (double)acc[i][j];
-                    else
-                        x = dacc[i][j] + (double)acc[i][j];
-                    const double cov = __builtin_fma(dN, x, -dST * (double)stat_s[o]);
-                    const float key = (float)cov * stat_r[o];
-                    const int iota = ((g.loz + dz + p.w) * side + (g.loy + yy + p.w)) * side +
-                                     (g.lox + xx + p.w);
-                    better(bk, bi, key, iota);
-                }
-            }
-    }
-    wg_argmax(bk, bi, s_key, s_idx);
-    if (bi == INT_MAX) {  // no finite key (cannot happen for 12-bit input): report, never index
-        if (tid == 0) write_result(p, blk, 0, 0, 0, NAN);
-        return;
-    }
-
-    // ---- exact NCC at the winning displacement (integer sums of raw voxels)
-    const int ddx = bi % side - p.w, ddy = (bi / side) % side - p.w, ddz = bi / (side * side) - p.w;
-    long long sums[5] = {0, 0, 0, 0, 0};  // T, T^2, F, F^2, TF
-    for (int o = tid; o < N; o += NT) {
-        const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        const long long tv = ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx +
-                                 (g.cx - H + ox)];
-        const long long fv = flt[((int64_t)(g.cz - H + ddz + oz) * p.ny + (g.cy - H + ddy + oy)) *
-                                     p.nx +
-                                 (g.cx - H + ddx + ox)];
-        sums[0] += tv;
-        sums[1] += tv * tv;
-        sums[2] += fv;
-        sums[3] += fv * fv;
-        sums[4] += tv * fv;
-    }
-    wg_sum<long long, 5>(sums, s_red);
-    if (tid == 0) {
-        const long long vt = (long long)N * sums[1] - sums[0] * sums[0];
-        const long long vf = (long long)N * sums[3] - sums[2] * sums[2];
-        const long long cv = (long long)N * sums[4] - sums[0] * sums[2];
-        const double v = (vt > 0 && vf > 0) ? (double)cv / sqrt((double)vt * (double)vf) : 0.0;
-        write_result(p, blk, ddx, ddy, ddz, (float)v);
-    }
-}
-
-// ---------------------------------------------------------- float volumes
-
-template <int B, int RX, int RY>
-__global__ __launch_bounds__(NT) void k_match_f32(Params p) {
-    constexpr int H = (B - 1) / 2, BP = (B + 3) & ~3, N = B * B * B;
-    extern __shared__ __align__(16) unsigned char lds[];
-    float *tf = reinterpret_cast<float *>(lds);            // [B][B][BP]
-    float *win = reinterpret_cast<float *>(lds + B * B * BP * 4);  // [PZ][PY][PX]
-    __shared__ double s_key[NT / 64];
-    __shared__ int s_idx[NT / 64];
-    __shared__ double s_red[(NT / 64) * 3];
-
-    const int64_t blk = p.first + xcd_block(blockIdx.x, gridDim.x);
-    const Geom g = make_geom(p, blk, H);
-    const int tid = threadIdx.x;
-    if (!g.inside) {
-        if (tid == 0) write_result(p, blk, 0, 0, 0, NAN);
-        return;
-    }
-    const float *ref = static_cast<const float *>(p.ref);
-    const float *flt = static_cast<const float *>(p.flt);
-    const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
-    const int PX = (txn * RX + B - 1 + 3) & ~3, PY = tyn * RY + B - 1, PZ = g.dz + B - 1;
+    const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1;
-
     auto tval = [&](int o) {
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        return (double)ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx +
-                           (g.cx - H + ox)];
+        return ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx + (g.cx - H + ox)];
     };
-    // ---- mean of T, centred T^ (float) and its FP64 sums
-    double r1[1] = {0.0};
-    for (int o = tid; o < N; o += NT) r1[0] += tval(o);
-    wg_sum<double, 1>(r1, s_red);
-    const double tmean = r1[0] / (double)N;
-    const float c = (float)tmean;
-    double r2[2] = {0.0, 0.0};  // sum T^, sum T^^2 of the float values used
-    for (int i = tid; i < B * B * BP; i += NT) {
-        const int oz = i / (B * BP), oy = (i / BP) % B, ox = i % BP;
-        float v = 0.0f;
-        if (ox < B) {
-            v = (float)(tval((oz * B + oy) * B + ox) - tmean);
-            r2[0] += (double)v;
-            r2[1] += (double)v * (double)v;
+
+    // ---- block statistics and the staged T table
+    const int plane = PY * PX + ZPAD;  // one pad dword per plane spreads LDS banks
+    auto stage_chunk = [&](int zc0, int ezc, float c) {
+        if constexpr (ARITH == DOT2)
+            stage_planes<NT, true>(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win,
+                                   PX, plane, PY, ezc, [](Vox a, Vox b, bool nb) {
+                                       const int hi = nb ? (int)b - 2048 : 0;
+                                       return (uint32_t)(uint16_t)((int)a - 2048) |
+                                              ((uint32_t)(uint16_t)hi << 16);
+                                   });
+        else
+            stage_planes<NT, false>(
+                flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win, PX, plane, PY, ezc,
+                [c](Vox a, Vox, bool) { return __float_as_uint((float)a - c); });
+    };
+    long long st[2] = {0, 0};  // 12-bit: exact sums of T and T^2
+    double tmean;
+    long long sT = 0;   // DOT2: sum (T - 2048)
+    double sTc = 0.0;   // FMA: sum of the centred float T^ actually used
+    float c = 0.0f;     // FMA: F is staged as F - c
+    if constexpr (ARITH == DOT2) {
+        // one pass: each T voxel is read once, into its plane-pair word, and
+        // counted into the exact sums; the first window chunk's loads are
+        // issued before the reduction's barrier so both latencies overlap
+        for (int i = tid; i < TP_WORDS; i += NT) {
+            const int pl = i / (B * BP), oy = (i / BP) % B, ox = i % BP;
+            uint32_t w = 0;
+            if (ox < B) {
+                const int z0 = 2 * pl, z1 = 2 * pl + 1;
+                const int lo = (int)tval((z0 * B + oy) * B + ox);
+                const int hi = z1 < B ? (int)tval((z1 * B + oy) * B + ox) : 2048;
+                st[0] += lo + (z1 < B ? hi : 0);
+                st[1] += (long long)lo * lo + (z1 < B ? (long long)hi * hi : 0);
+                w = (uint32_t)(uint16_t)(lo - 2048) | ((uint32_t)(uint16_t)(hi - 2048) << 16);
+            }
+            tp[i] = w;
         }
-        tf[i] = v;
-    }
-    stage_box(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0, ex, ey, PZ, win, PX, PY, PZ,
-              [c](float v) { return v - c; });
-    wg_sum<double, 2>(r2, s_red);
-    const double sT = r2[0];
-    if (!(r2[1] > 0.0)) {  // flat block
-        if (tid == 0) write_result(p, blk, g.lox, g.loy, g.loz, 0.0f);
-        return;
+        stage_chunk(0, min(p.cz, g.dz) + B - 1, 0.0f);
+        wg_sum<NT, long long, 2>(st, s_red);  // its barrier also publishes tp and the window
+        if ((long long)N * st[1] - st[0] * st[0] == 0) {  // flat block: all NCC are 0
+            if (tid == 0) write_result(p, blk, g.lox, g.loy, g.loz, 0.0f);
+            return;
+        }
+        tmean = (double)st[0] / (double)N;
+        sT = st[0] - 2048ll * N;
+    } else {
+        double sd[1] = {0.0};
+        for (int o = tid; o < N; o += NT) {
+            const Vox v = tval(o);
+            if constexpr (U16) {
+                st[0] += v;
+                st[1] += (long long)v * v;
+            }
+            sd[0] += (double)v;
+        }
+        wg_sum<NT, double, 1>(sd, s_redd);
+        tmean = sd[0] / (double)N;
+        if constexpr (U16) wg_sum<NT, long long, 2>(st, s_red);
+        // 12-bit data keep c an integer (exact floats)
+        c = U16 ? (float)llrint(tmean) : (float)tmean;
+        double ctr[2] = {0.0, 0.0};  // sum T^, sum T^^2 of the float values used
+        for (int i = tid; i < TP_WORDS; i += NT) {
+            const int pl = i / (B * BP), oy = (i / BP) % B, ox = i % BP;
+            uint32_t w = 0;
+            if (ox < B) {
+                const float v = (float)((double)tval((pl * B + oy) * B + ox) - tmean);
+                ctr[0] += (double)v;
+                ctr[1] += (double)v * (double)v;
+                w = __float_as_uint(v);
+            }
+            tp[i] = w;
+        }
+        stage_chunk(0, min(p.cz, g.dz) + B - 1, c);
+        wg_sum<NT, double, 2>(ctr, s_redd);  // barrier publishes tp and the window
+        sTc = ctr[0];
+        if (!(ctr[1] > 0.0)) {  // flat block
+            if (tid == 0) write_result(p, blk, g.lox, g.loy, g.loz, 0.0f);
+            return;
+        }
     }
 
-    const double *stat_s = static_cast<const double *>(p.stat_s);
-    const double *stat_r = static_cast<const double *>(p.stat_r);
-    const double dN = (double)N, nc = dN * (double)c;
+    // ---- exhaustive search, one z-chunk of displacement planes at a time
+    const double dN = (double)N;
     const int side = 2 * p.w + 1;
-    double bk = -INFINITY;
+    KeyT bk = -INFINITY;
     int bi = INT_MAX;
-    const int ntiles = txn * tyn * g.dz;
-    const int plane = PY * PX;
-    for (int t = tid; t < ntiles; t += NT) {
-        const int tx = t % txn, ty = (t / txn) % tyn, dz = t / (txn * tyn);
-        float acc[RX][RY];
+    for (int zc0 = 0; zc0 < g.dz; zc0 += p.cz) {
+        const int czn = min(p.cz, g.dz - zc0);  // displacement planes in this chunk
+        const int ezc = czn + B - 1;            // window planes in this chunk
+        if (zc0 > 0) {                          // the first chunk was staged above
+            __syncthreads();                    // previous chunk fully consumed
+            stage_chunk(zc0, ezc, c);
+            __syncthreads();
+        }
+        const int ntiles = txn * tyn * czn;
+        for (int t = tid; t < ntiles; t += NT) {
+            // consecutive lanes take consecutive dz (then x, then y tiles): with
+            // the plane padding this spreads a wavefront's reads over the banks
+            const int dzl = t % czn, tx = (t / czn) % txn, ty = t / (czn * txn);
+            const int dz = zc0 + dzl;
+            const uint32_t *base = win + dzl * plane + ty * RY * PX + tx * RX;
+            // the tile's table records: all loaded at once (coordinates clamped
+            // into the valid range, so every load is in bounds), either before
+            // the multiply loop (PF: their latency hides behind it) or after
+            using Rec = typename std::conditional<U16, StatU16, StatF32>::type;
+            const Rec *table = static_cast<const Rec *>(p.stats);
+            Rec rec[RX][RY];
+            const int64_t zrow = (int64_t)(g.wz0 + dz) * p.oy;
+            auto load_recs = [&]() {
 #pragma unroll
-        for (int i = 0; i < RX; ++i)
+                for (int j = 0; j < RY; ++j)
 #pragma unroll
-            for (int j = 0; j < RY; ++j) acc[i][j] = 0.0f;
-        const float *base = win + (dz * PY + ty * RY) * PX + tx * RX;
-        for (int oz = 0; oz < B; ++oz) {
-            float tq[B][B];
-            const float *tz = tf + oz * B * BP;
+                    for (int i = 0; i < RX; ++i) {
+                        const int xx = min(tx * RX + i, g.dx - 1), yy = min(ty * RY + j, g.dy - 1);
+                        rec[i][j] = table[(zrow + (g.wy0 + yy)) * p.ox + (g.wx0 + xx)];
+                    }
+            };
+            if constexpr (PF) load_recs();
+            double xacc[RX][RY];  // cross term of each displacement of the tile
+            if constexpr (ARITH == DOT2) {
+                int acc[RX][RY], acc0[RX][RY];
+                double dacc[NG > 2 ? RX : 1][NG > 2 ? RY : 1];
 #pragma unroll
-            for (int oy = 0; oy < B; ++oy)
+                for (int i = 0; i < RX; ++i)
 #pragma unroll
-                for (int ox = 0; ox < B; ++ox) tq[oy][ox] = tz[oy * BP + ox];
-            const float *w0 = base + oz * plane;
+                    for (int j = 0; j < RY; ++j) {
+                        acc[i][j] = 0;
+                        acc0[i][j] = 0;
+                        if constexpr (NG > 2) dacc[i][j] = 0.0;
+                    }
+                for (int m = 0; m < P; ++m) {
+                    int tq[B][B];
+                    const uint32_t *tpm = tp + m * B * BP;
 #pragma unroll
-            for (int yw = 0; yw < RY + B - 1; ++yw) {
-                float f[RX + B - 1];
+                    for (int oy = 0; oy < B; ++oy)
 #pragma unroll
-                for (int xw = 0; xw < RX + B - 1; ++xw) f[xw] = w0[yw * PX + xw];
+                        for (int ox = 0; ox < B; ++ox) tq[oy][ox] = (int)tpm[oy * BP + ox];
+                    const lds_word *wm = (const lds_word *)(base + 2 * m * plane);
+                    // rows are software-pipelined: row yw+1 is read while row yw
+                    // is multiplied
+                    int fr[2][RX + B - 1];
 #pragma unroll
-                for (int j = 0; j < RY; ++j) {
-                    const int oy = yw - j;
-                    if (oy < 0 || oy >= B) continue;
+                    for (int xw = 0; xw < RX + B - 1; ++xw) fr[0][xw] = (int)wm[xw];
 #pragma unroll
-                    for (int i = 0; i < RX; ++i)
+                    for (int yw = 0; yw < RY + B - 1; ++yw) {
+                        if (yw + 1 < RY + B - 1) {
+#pragma unroll
+                            for (int xw = 0; xw < RX + B - 1; ++xw)
+                                fr[(yw + 1) & 1][xw] = (int)wm[(yw + 1) * PX + xw];
+                        }
+                        const int *f = fr[yw & 1];
+#pragma unroll
+                        for (int j = 0; j < RY; ++j) {
+                            const int oy = yw - j;
+                            if (oy < 0 || oy >= B) continue;
+#pragma unroll
+                            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                                for (int ox = 0; ox < B; ++ox)
+                                    acc[i][j] = __builtin_amdgcn_sdot2(
+                                        __builtin_bit_cast(short2v, f[i + ox]),
+                                        __builtin_bit_cast(short2v, tq[oy][ox]), acc[i][j],
+                                        false);
+                        }
+                    }
+                    if constexpr (NG == 2) {
+                        if (m == GP - 1) {
+#pragma unroll
+                            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                                for (int j = 0; j < RY; ++j) {
+                                    acc0[i][j] = acc[i][j];
+                                    acc[i][j] = 0;
+                                }
+                        }
+                    } else if constexpr (NG > 2) {
+                        if ((m + 1) % GP == 0) {
+#pragma unroll
+                            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                                for (int j = 0; j < RY; ++j) {
+                                    dacc[i][j] += (double)acc[i][j];
+                                    acc[i][j] = 0;
+                                }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        if constexpr (NG == 1)
+                            xacc[i][j] = (double)acc[i][j];
+                        else if constexpr (NG == 2)
+                            xacc[i][j] = (double)acc0[i][j] + (double)acc[i][j];
+                        else
+                            xacc[i][j] = dacc[i][j] + (double)acc[i][j];
+                    }
+            } else {
+                float acc[RX][RY];
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) acc[i][j] = 0.0f;
+                for (int oz = 0; oz < B; ++oz) {
+                    float tq[B][B];
+                    const uint32_t *tpz = tp + oz * B * BP;
+#pragma unroll
+                    for (int oy = 0; oy < B; ++oy)
 #pragma unroll
                         for (int ox = 0; ox < B; ++ox)
-                            acc[i][j] = __builtin_fmaf(f[i + ox], tq[oy][ox], acc[i][j]);
+                            tq[oy][ox] = __uint_as_float(tpz[oy * BP + ox]);
+                    const lds_word *wz = (const lds_word *)(base + oz * plane);
+                    float fr[2][RX + B - 1];
+#pragma unroll
+                    for (int xw = 0; xw < RX + B - 1; ++xw) fr[0][xw] = __uint_as_float(wz[xw]);
+#pragma unroll
+                    for (int yw = 0; yw < RY + B - 1; ++yw) {
+                        if (yw + 1 < RY + B - 1) {
+#pragma unroll
+                            for (int xw = 0; xw < RX + B - 1; ++xw)
+                                fr[(yw + 1) & 1][xw] = __uint_as_float(wz[(yw + 1) * PX + xw]);
+                        }
+                        const float *f = fr[yw & 1];
+#pragma unroll
+                        for (int j = 0; j < RY; ++j) {
+                            const int oy = yw - j;
+                            if (oy < 0 || oy >= B) continue;
+#pragma unroll
+                            for (int i = 0; i < RX; ++i)
+#pragma unroll
+                                for (int ox = 0; ox < B; ++ox)
+                                    acc[i][j] = __builtin_fmaf(f[i + ox], tq[oy][ox], acc[i][j]);
+                        }
+                    }
                 }
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) xacc[i][j] = (double)acc[i][j];
             }
+            // ---- rank the tile's displacements: key = N*cov * rsqrt(N*varF);
+            // invalid displacements are masked, no branch per displacement
+            if constexpr (!PF) load_recs();
+            const int irow = ((g.loz + dz + p.w) * side + (g.loy + ty * RY + p.w)) * side +
+                             (g.lox + tx * RX + p.w);
+            // sum of the staged F: DOT2 F-2048 (= the table's s), FMA F-c
+            const double fshift = ARITH == DOT2 ? 0.0 : dN * (2048.0 - (double)c);
+            const double tsum = ARITH == DOT2 ? (double)sT : sTc;
+            KeyT tk = -INFINITY;
+            int ti = INT_MAX;
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+#pragma unroll
+                for (int i = 0; i < RX; ++i) {  // increasing shift index
+                    const bool valid = tx * RX + i < g.dx && ty * RY + j < g.dy;
+                    KeyT key;
+                    if constexpr (U16) {
+                        const double cov =
+                            __builtin_fma(dN, xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
+                        key = (float)cov * rec[i][j].r;
+                    } else {
+                        const double cov = dN * xacc[i][j] - sTc * (rec[i][j].s - dN * (double)c);
+                        key = cov * rec[i][j].r;
+                    }
+                    const bool take = valid && key > tk;  // ties keep the smaller index
+                    tk = take ? key : tk;
+                    ti = take ? irow + j * side + i : ti;
+                }
+            better(bk, bi, tk, ti);
         }
-#pragma unroll
-        for (int i = 0; i < RX; ++i)
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                const int xx = tx * RX + i, yy = ty * RY + j;
-                if (xx < g.dx && yy < g.dy) {
-                    const int64_t o = ((int64_t)(g.wz0 + dz) * p.oy + (g.wy0 + yy)) * p.ox +
-                                      (g.wx0 + xx);
-                    // cov * N = N * sum T^(F-c) - sum T^ * (sum F - N c)
-                    const double cov = dN * (double)acc[i][j] - sT * (stat_s[o] - nc);
-                    const double key = cov * stat_r[o];
-                    const int iota = ((g.loz + dz + p.w) * side + (g.loy + yy + p.w)) * side +
-                                     (g.lox + xx + p.w);
-                    better(bk, bi, key, iota);
-                }
-            }
     }
-    wg_argmax(bk, bi, s_key, s_idx);
+    wg_argmax<NT>(bk, bi, s_key, s_idx);
     if (bi == INT_MAX) {  // every key NaN (non-finite input): report, never index
         if (tid == 0) write_result(p, blk, 0, 0, 0, NAN);
         return;
     }
 
-    // ---- exact two-pass FP64 NCC at the winning displacement
+    // ---- exact NCC at the winning displacement, from the volumes
     const int ddx = bi % side - p.w, ddy = (bi / side) % side - p.w, ddz = bi / (side * side) - p.w;
     auto fval = [&](int o) {
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        return (double)flt[((int64_t)(g.cz - H + ddz + oz) * p.ny + (g.cy - H + ddy + oy)) * p.nx +
-                           (g.cx - H + ddx + ox)];
+        return flt[((int64_t)(g.cz - H + ddz + oz) * p.ny + (g.cy - H + ddy + oy)) * p.nx +
+                   (g.cx - H + ddx + ox)];
     };
-    double m2[1] = {0.0};
-    for (int o = tid; o < N; o += NT) m2[0] += fval(o);
-    wg_sum<double, 1>(m2, s_red);
-    const double fmean = m2[0] / (double)N;
-    double q[3] = {0.0, 0.0, 0.0};  // A, B, X
-    for (int o = tid; o < N; o += NT) {
-        const double a = tval(o) - tmean, b = fval(o) - fmean;
-        q[0] += a * a;
-        q[1] += b * b;
-        q[2] += a * b;
-    }
-    wg_sum<double, 3>(q, s_red);
-    if (tid == 0) {
-        const double ab = q[0] * q[1];
-        const double v = ab > 0.0 ? q[2] / sqrt(ab) : 0.0;
-        write_result(p, blk, ddx, ddy, ddz, (float)v);
+    if constexpr (U16) {
+        // the exact sums of T and T^2 are already known (st); F and TF here
+        long long sums[3] = {0, 0, 0};  // F, F^2, TF (raw 12-bit values)
+        for (int o = tid; o < N; o += NT) {
+            const long long tv = tval(o), fv = fval(o);
+            sums[0] += fv;
+            sums[1] += fv * fv;
+            sums[2] += tv * fv;
+        }
+        wg_sum<NT, long long, 3>(sums, s_red);
+        if (tid == 0) {
+            const long long vt = (long long)N * st[1] - st[0] * st[0];
+            const long long vf = (long long)N * sums[1] - sums[0] * sums[0];
+            const long long cv = (long long)N * sums[2] - st[0] * sums[0];
+            const double v = (vt > 0 && vf > 0) ? (double)cv / sqrt((double)vt * (double)vf) : 0.0;
+            write_result(p, blk, ddx, ddy, ddz, (float)v);
+        }
+    } else {
+        double m2[1] = {0.0};
+        for (int o = tid; o < N; o += NT) m2[0] += (double)fval(o);
+        wg_sum<NT, double, 1>(m2, s_redd);
+        const double fmean = m2[0] / (double)N;
+        double q[3] = {0.0, 0.0, 0.0};  // A, B, X of the two-pass Pearson form
+        for (int o = tid; o < N; o += NT) {
+            const double a = (double)tval(o) - tmean, b = (double)fval(o) - fmean;
+            q[0] += a * a;
+            q[1] += b * b;
+            q[2] += a * b;
+        }
+        wg_sum<NT, double, 3>(q, s_redd);
+        if (tid == 0) {
+            const double ab = q[0] * q[1];
+            const double v = ab > 0.0 ? q[2] / sqrt(ab) : 0.0;
+            write_result(p, blk, ddx, ddy, ddz, (float)v);
+        }
     }
 }
 
@@ -560,56 +600,140 @@ typedef void (*kernel_t)(Params);
 
 struct Variant {
     nrr_dtype dtype;
-    int b, rx, ry;
+    int arith, b, rx, ry, nt, pf;
     kernel_t fn;
 };
 
-#define U16V(B, RX, RY) {NRR_U16, B, RX, RY, k_match_u16<B, RX, RY>}
-#define F32V(B, RX, RY) {NRR_F32, B, RX, RY, k_match_f32<B, RX, RY>}
+#define V16D(B, RX, RY, NT, PF) \
+    {NRR_U16, DOT2, B, RX, RY, NT, PF, k_match<uint16_t, DOT2, B, RX, RY, NT, PF>}
+#define V16F(B, RX, RY, NT, PF) \
+    {NRR_U16, FMA, B, RX, RY, NT, PF, k_match<uint16_t, FMA, B, RX, RY, NT, PF>}
+#define V32F(B, RX, RY, NT, PF) \
+    {NRR_F32, FMA, B, RX, RY, NT, PF, k_match<float, FMA, B, RX, RY, NT, PF>}
 
 const Variant kVariants[] = {
-    U16V(3, 4, 4),  U16V(3, 3, 7),  U16V(3, 5, 5),  U16V(5, 4, 4),  U16V(5, 3, 7),
-    U16V(5, 5, 5),  U16V(7, 4, 4),  U16V(7, 3, 7),  U16V(7, 5, 5),  U16V(9, 4, 4),
-    U16V(9, 3, 7),  U16V(9, 5, 5),  U16V(11, 3, 3), U16V(13, 3, 3), U16V(15, 2, 2),
-    F32V(3, 4, 4),  F32V(5, 4, 4),  F32V(7, 4, 4),  F32V(9, 4, 4),  F32V(11, 3, 3),
-    F32V(13, 3, 3), F32V(15, 2, 2),
+    V16D(3, 4, 4, 256, 0),  V16D(5, 4, 4, 256, 0),  V16D(5, 3, 7, 448, 0),
+    V16D(7, 4, 4, 256, 0),  V16D(7, 3, 7, 448, 0),  V16D(7, 3, 7, 256, 0),
+    V16D(7, 3, 7, 256, 1),  V16D(7, 3, 7, 448, 1),  V16D(7, 3, 5, 256, 0),
+    V16D(7, 5, 5, 256, 0),  V16D(9, 4, 4, 256, 0),  V16D(9, 5, 5, 256, 0),
+    V16D(11, 3, 3, 256, 0), V16D(13, 3, 3, 256, 0), V16D(15, 2, 2, 256, 0),
+    V16F(3, 4, 4, 256, 0),  V16F(5, 4, 4, 256, 0),  V16F(5, 3, 7, 448, 0),
+    V16F(7, 4, 4, 256, 0),  V16F(7, 3, 7, 448, 0),  V16F(9, 4, 4, 256, 0),
+    V16F(9, 5, 5, 256, 0),  V16F(11, 3, 3, 256, 0), V16F(13, 3, 3, 256, 0),
+    V16F(15, 2, 2, 256, 0), V32F(3, 4, 4, 256, 0),  V32F(5, 4, 4, 256, 0),
+    V32F(7, 4, 4, 256, 0),  V32F(7, 3, 7, 448, 0),  V32F(9, 4, 4, 256, 0),
+    V32F(11, 3, 3, 256, 0), V32F(13, 3, 3, 256, 0), V32F(15, 2, 2, 256, 0),
 };
 
-size_t lds_bytes(nrr_dtype dtype, int b, int rx, int ry, int w) {
+struct Plan {
+    const Variant *v;
+    int cz;
+    size_t lds;
+};
+
+size_t t_table_bytes(const Variant &v) {
+    const int bp = (v.b + 3) & ~3;
+    const int planes = v.arith == DOT2 ? (v.b + 1) / 2 : v.b;
+    return (size_t)planes * v.b * bp * 4;
+}
+
+size_t window_plane_bytes(const Variant &v, int w) {
     const int d = 2 * w + 1;
-    const int px = ((d + rx - 1) / rx * rx + b - 1 + 3) & ~3, py = (d + ry - 1) / ry * ry + b - 1;
-    const int bp = (b + 3) & ~3;
-    if (dtype == NRR_U16) {
-        const int pz = d + b;
-        return (size_t)((b + 1) / 2) * b * bp * 4 + (size_t)pz * py * px * 2;
+    const int px = (d + v.rx - 1) / v.rx * v.rx + v.b - 1;
+    const int py = (d + v.ry - 1) / v.ry * v.ry + v.b - 1;
+    return ((size_t)px * py + ZPAD) * 4;
+}
+
+// z-chunk and LDS size: the whole window if it fits in `target` bytes (two
+// workgroups per CU), else the largest balanced chunk of displacement planes
+// that still fits in `target`, else the largest that fits in `limit`.
+// Re-staging the b-1 overlap planes of each chunk is cheap next to the search.
+bool plan_variant(const Variant &v, int w, size_t limit, size_t target, Plan *out) {
+    const int d = 2 * w + 1;
+    const size_t fixed = t_table_bytes(v) + 2048;  // + static shared and slack
+    const size_t pb = window_plane_bytes(v, w);
+    if (fixed + (size_t)v.b * pb > limit) return false;
+    int cz = d;
+    if (fixed + (size_t)(cz + v.b - 1) * pb > target) {
+        const size_t cap = fixed + (size_t)v.b * pb <= target ? target : limit;
+        const long fit = (long)((cap - fixed) / pb) - (v.b - 1);
+        cz = (int)(fit < d ? fit : d);
+        const int nch = (d + cz - 1) / cz;
+        cz = (d + nch - 1) / nch;
     }
-    const int pz = d + b - 1;
-    return (size_t)b * b * bp * 4 + (size_t)pz * py * px * 4;
+    out->v = &v;
+    out->cz = cz;
+    out->lds = t_table_bytes(v) + (size_t)(cz + v.b - 1) * pb;
+    return true;
 }
 
-// Cost model for choosing the displacement tile: padded tiles times the
-// per-tile instruction count (multiply-adds plus LDS element reads).
-double tile_cost(const Variant &v, int w) {
+// Cost model: padded displacement work over the workgroup's thread rounds.
+double plan_cost(const Plan &pl, int w) {
+    const Variant &v = *pl.v;
     const int d = 2 * w + 1;
-    const double tiles = (double)((d + v.rx - 1) / v.rx) * ((d + v.ry - 1) / v.ry);
-    const double per = (double)v.rx * v.ry * v.b * v.b +
-                       (v.dtype == NRR_U16 ? 2.0 : 1.0) * (v.rx + v.b - 1) * (v.ry + v.b - 1);
-    return tiles * per;
+    const double tiles = (double)((d + v.rx - 1) / v.rx) * ((d + v.ry - 1) / v.ry) * pl.cz;
+    const double rounds = std::ceil(tiles / v.nt) * ((d + pl.cz - 1) / pl.cz);
+    const double planes = v.arith == DOT2 ? (v.b + 1) / 2 : v.b;
+    // instructions per tile: multiply-adds (dot2 issues at half the FMA rate)
+    const double per = planes * v.rx * v.ry * v.b * v.b * (v.arith == DOT2 ? 2.0 : 1.0) +
+                       planes * (v.rx + v.b - 1) * (v.ry + v.b - 1);
+    return rounds * v.nt * per;
 }
 
-const Variant *choose(nrr_dtype dtype, int b, int w, size_t limit) {
-    const Variant *best = nullptr;
-    double bc = 0.0;
-    for (const Variant &v : kVariants) {
-        if (v.dtype != dtype || v.b != b) continue;
-        if (lds_bytes(dtype, b, v.rx, v.ry, w) + 1024 > limit) continue;
-        const double c = tile_cost(v, w);
-        if (!best || c < bc) {
-            best = &v;
-            bc = c;
+int arith_preference() {
+    const char *e = getenv("NRR_ARITH");
+    if (!e) return -1;
+    if (!strcmp(e, "dot2")) return DOT2;
+    if (!strcmp(e, "fma")) return FMA;
+    return -1;
+}
+
+// Tuning overrides (for measurement sweeps and the tile tuner): NRR_TILE=
+// "rx,ry,nt[,pf]" restricts the variant, NRR_CZ=n caps the z-chunk.  Unknown or
+// infeasible values are ignored.
+void tile_override(int *rx, int *ry, int *nt, int *pf, int *cz) {
+    *rx = *ry = *nt = *cz = 0;
+    *pf = -1;
+    if (const char *e = getenv("NRR_TILE")) sscanf(e, "%d,%d,%d,%d", rx, ry, nt, pf);
+    if (const char *e = getenv("NRR_CZ")) *cz = atoi(e);
+}
+
+bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, Plan *best) {
+    int orx, ory, ont, opf, ocz;
+    tile_override(&orx, &ory, &ont, &opf, &ocz);
+    for (int pass = 0; pass < 2; ++pass) {  // pass 0 honours the overrides
+        bool found = false;
+        double bc = 0.0;
+        for (const Variant &v : kVariants) {
+            if (v.dtype != dtype || v.b != b) continue;
+            if (arith >= 0 && v.arith != arith) continue;
+            if (pass == 0 && orx > 0 && (v.rx != orx || v.ry != ory || v.nt != ont)) continue;
+            if (pass == 0 && opf >= 0 && v.pf != opf) continue;
+            Plan pl;
+            if (!plan_variant(v, w, limit, limit / 2, &pl)) continue;
+            if (pass == 0 && ocz > 0 && ocz < pl.cz) {
+                const int d = 2 * w + 1, nch = (d + ocz - 1) / ocz;
+                pl.cz = (d + nch - 1) / nch;
+                pl.lds = t_table_bytes(v) + (size_t)(pl.cz + v.b - 1) * window_plane_bytes(v, w);
+            }
+            const double c = plan_cost(pl, w);
+            if (!found || c < bc) {
+                *best = pl;
+                bc = c;
+                found = true;
+            }
         }
+        if (found) return true;
     }
-    return best;
+    return false;
+}
+
+// NRR_ARITH=dot2|fma restricts 12-bit volumes to one arithmetic form (float
+// volumes only have the FMA form); otherwise the cost model decides.
+bool choose(nrr_dtype dtype, int b, int w, size_t limit, Plan *best) {
+    const int pref = arith_preference();
+    if (pref >= 0 && choose_with(dtype, b, w, limit, pref, best)) return true;
+    return choose_with(dtype, b, w, limit, -1, best);
 }
 
 }  // namespace
@@ -633,18 +757,18 @@ size_t device_lds_limit() {
 const char *match_unsupported_reason(nrr_dtype dtype, int32_t block, int32_t window) {
     if (block > MAX_B) return "block edge above 15 is not built";
     if (window > 64) return "window above 64 is not supported";
-    if (!choose(dtype, block, window, device_lds_limit()))
-        return "search window does not fit in LDS for this block size";
+    Plan pl;
+    if (!choose(dtype, block, window, device_lds_limit(), &pl))
+        return "one window plane does not fit in LDS for this block size";
     return nullptr;
 }
 
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream) {
-    const size_t limit = device_lds_limit();
-    const Variant *v = choose(dtype, a.block, a.window, limit);
-    if (!v) return hipErrorInvalidValue;
-    const size_t lds = lds_bytes(dtype, a.block, v->rx, v->ry, a.window);
+    Plan pl;
+    if (!choose(dtype, a.block, a.window, device_lds_limit(), &pl)) return hipErrorInvalidValue;
+    const Variant *v = pl.v;
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(v->fn),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds) != hipSuccess)
         return hipGetLastError();
     Params p;
     p.ref = a.ref;
@@ -655,8 +779,8 @@ hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream)
     p.centers = a.centers;
     p.n = a.n;
     p.w = a.window;
-    p.stat_s = a.stat_s;
-    p.stat_r = a.stat_r;
+    p.cz = pl.cz;
+    p.stats = a.stats;
     p.ox = a.ox;
     p.oy = a.oy;
     p.disp = a.disp;
@@ -666,7 +790,7 @@ hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream)
     for (int64_t first = 0; first < a.n; first += chunk) {
         p.first = first;
         const int64_t cnt = a.n - first < chunk ? a.n - first : chunk;
-        hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(NT), lds, stream, p);
+        hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(v->nt), pl.lds, stream, p);
     }
     return hipGetLastError();
 }

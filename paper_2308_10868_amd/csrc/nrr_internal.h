@@ -28,13 +28,21 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
 
 // ---------------------------------------------------------- window stats
 // Per-voxel statistics of the displaced block whose origin (lowest corner)
-// is that voxel, over the origin grid O = dims - block + 1:
-//   u16: s  = sum (F - 2048)          (int32, exact)
-//        r  = 1/sqrt(N*sum (F-2048)^2 - s^2)  (float; 0 for a flat block)
-//   f32: s  = sum F                   (double)
-//        r  = 1/sqrt(N*sum F^2 - s^2) (double; 0 for a flat block)
+// is that voxel, over the origin grid O = dims - block + 1, one record per
+// origin (interleaved so the search reads one record per displacement):
+//   u16: s = sum (F - 2048) (exact), r = 1/sqrt(N*sum (F-2048)^2 - s^2)
+//        (ranking only; 0 for a flat block)
+//   f32: s = sum F, r = 1/sqrt(N*sum F^2 - s^2) (0 for a flat block)
+struct StatU16 {
+    int32_t s;
+    float r;
+};
+struct StatF32 {
+    double s;
+    double r;
+};
 struct StatsLayout {
-    size_t s_off, r_off, total;
+    size_t total;
     int32_t ox, oy, oz;
 };
 StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
@@ -50,8 +58,7 @@ struct MatchArgs {
     const int32_t *centers;
     int64_t n;
     int32_t block, window;
-    const void *stat_s;  // int32 (u16) or double (f32)
-    const void *stat_r;  // float (u16) or double (f32)
+    const void *stats;   // StatU16 or StatF32 records, [oz][oy][ox]
     int32_t ox, oy;      // origin-grid extents (x, y) of the stats arrays
     int32_t *disp;
     float *ncc;

@@ -119,7 +119,12 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
     __syncthreads();
     // skip leading bytes that are zero in every key
     uint64_t orv = 0;
-    for (int64_t i = tid; i < n; i += blockDim.x) orv |= keys[i];
+    for (int64_t i = tid; i < n; i += 4 * blockDim.x) {
+        orv |= keys[i];
+        if (i + blockDim.x < n) orv |= keys[i + blockDim.x];
+        if (i + 2 * blockDim.x < n) orv |= keys[i + 2 * blockDim.x];
+        if (i + 3 * blockDim.x < n) orv |= keys[i + 3 * blockDim.x];
+    }
     for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off);
     if ((tid & 63) == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
     __syncthreads();
@@ -129,12 +134,21 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
         for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix, mask = s_mask;
+        constexpr int UNR = 8;  // keys loaded per thread before any is counted
         const int64_t iters = (n + blockDim.x - 1) / blockDim.x;
-        for (int64_t it = 0; it < iters; ++it) {  // uniform trip count: ballots stay convergent
-            int64_t i = it * blockDim.x + tid;
-            uint64_t key = i < n ? keys[i] : 0;
-            bool valid = i < n && (key & mask) == prefix;
-            hist_add(hist, (uint32_t)((key >> shift) & 0xff), valid);
+        for (int64_t it = 0; it < iters; it += UNR) {  // uniform trip count: ballots converge
+            uint64_t kv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = (it + u) * blockDim.x + tid;
+                kv[u] = i < n ? keys[i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t i = (it + u) * blockDim.x + tid;
+                const bool valid = i < n && (kv[u] & mask) == prefix;
+                hist_add(hist, (uint32_t)((kv[u] >> shift) & 0xff), valid);
+            }
         }
         __syncthreads();
         if (tid < 64) {  // wavefront 0: find the digit holding the need-th largest key

@@ -70,15 +70,18 @@ def _streams(seed: int, n: int):
 
 
 def _blob_field(shape_zyx, centres, sigmas, amps, offset=(0.0, 0.0, 0.0), support=None):
-    """Sum of isotropic Gaussian blobs evaluated at voxel centres.
+    """Sum of isotropic Gaussian blobs evaluated at voxel centres (float64).
 
     ``offset`` (x, y, z) evaluates the field at ``p - offset`` (a translated
     copy, computed analytically so there are no border artefacts).  With
     ``support`` = k, each blob is evaluated on its +-k*sigma box only (the
-    separable factors make that an outer product).
+    separable factors make that an outer product).  Elementwise work runs in
+    multithreaded torch CPU ops; the result is deterministic.
     """
+    import torch
+
     nz, ny, nx = shape_zyx
-    out = np.zeros(shape_zyx, dtype=np.float64)
+    out = torch.zeros(shape_zyx, dtype=torch.float64)
     ox, oy, oz = offset
     for (cx, cy, cz), s, a in zip(centres, sigmas, amps):
         cx, cy, cz = cx + ox, cy + oy, cz + oz
@@ -92,11 +95,11 @@ def _blob_field(shape_zyx, centres, sigmas, amps, offset=(0.0, 0.0, 0.0), suppor
             if x0 >= x1 or y0 >= y1 or z0 >= z1:
                 continue
         inv = 1.0 / (2.0 * s * s)
-        gx = np.exp(-((np.arange(x0, x1) - cx) ** 2) * inv)
-        gy = np.exp(-((np.arange(y0, y1) - cy) ** 2) * inv)
-        gz = np.exp(-((np.arange(z0, z1) - cz) ** 2) * inv)
-        out[z0:z1, y0:y1, x0:x1] += a * (gz[:, None, None] * (gy[None, :, None] * gx[None, None, :]))
-    return out
+        gx = torch.from_numpy(np.exp(-((np.arange(x0, x1) - cx) ** 2) * inv))
+        gy = torch.from_numpy(np.exp(-((np.arange(y0, y1) - cy) ** 2) * inv))
+        gz = torch.from_numpy(a * np.exp(-((np.arange(z0, z1) - cz) ** 2) * inv))
+        out[z0:z1, y0:y1, x0:x1] += gz[:, None, None] * (gy[None, :, None] * gx[None, None, :])
+    return out.numpy()
 
 
 def gen_translation_f32(seed: int = 0, n: int = 64, n_blobs: int = 40,
@@ -134,19 +137,22 @@ def _sag_field(shape_zyx, n_sags, centre_lo, centre_hi, sigma_lo, sigma_hi, amp_
     peaks = rng.uniform(amp_lo, amp_hi, size=n_sags)
     dirs = rng.normal(size=(n_sags, 3))
     dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
-    ux = np.zeros(shape_zyx)
-    uy = np.zeros(shape_zyx)
-    uz = np.zeros(shape_zyx)
-    zz = np.arange(nz, dtype=np.float64)[:, None, None]
-    yy = np.arange(ny, dtype=np.float64)[None, :, None]
-    xx = np.arange(nx, dtype=np.float64)[None, None, :]
+    import torch
+
+    ux = torch.zeros(shape_zyx, dtype=torch.float64)
+    uy = torch.zeros(shape_zyx, dtype=torch.float64)
+    uz = torch.zeros(shape_zyx, dtype=torch.float64)
     for (cx, cy, cz), s, a, d in zip(centres, sigmas, peaks, dirs):
         inv = 1.0 / (2.0 * s * s)
-        g = a * (np.exp(-((zz - cz) ** 2) * inv) * np.exp(-((yy - cy) ** 2) * inv)
-                 * np.exp(-((xx - cx) ** 2) * inv))
-        ux += g * d[0]
-        uy += g * d[1]
-        uz += g * d[2]
+        ez = torch.from_numpy(a * np.exp(-((np.arange(nz) - cz) ** 2) * inv))
+        ey = torch.from_numpy(np.exp(-((np.arange(ny) - cy) ** 2) * inv))
+        ex = torch.from_numpy(np.exp(-((np.arange(nx) - cx) ** 2) * inv))
+        g = ez[:, None, None] * (ey[None, :, None] * ex[None, None, :])
+        ux.add_(g, alpha=float(d[0]))
+        uy.add_(g, alpha=float(d[1]))
+        uz.add_(g, alpha=float(d[2]))
+        del g
+    ux, uy, uz = ux.numpy(), uy.numpy(), uz.numpy()
     sags = [{"centre": c.tolist(), "sigma": float(s), "peak": float(a), "dir": d.tolist()}
             for c, s, a, d in zip(centres, sigmas, peaks, dirs)]
     return (ux, uy, uz), sags

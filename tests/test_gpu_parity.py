@@ -18,6 +18,14 @@ from tests.gpu_util import NCC_TOL, check_match, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(autouse=True, params=["fma", "dot2"])
+def arith(request, monkeypatch):
+    """Every case runs with both forms of the cross-term arithmetic: FP32 FMA
+    and the exact int16 dot2 form (12-bit data; float data always use FMA)."""
+    monkeypatch.setenv("NRR_ARITH", request.param)
+    return request.param
+
+
 def say(*a):
     print("[gpu-case]", *a, flush=True)
     sys.stdout.flush()
@@ -164,17 +172,26 @@ def test_self_match(torch_dev, dtype):
     assert np.all(np.abs(n - 1.0) <= 1e-6) and np.all(n <= 1.0 + 1e-6)
 
 
-def test_scale_by_two_bit_identical(torch_dev):
-    say("u16 x2 scale")
+def test_scale_by_two(torch_dev, arith):
+    """x2 intensities: selection is bit-identical (exact integer keys); the
+    exact dot2 form also gives bit-identical displacements and NCC (every
+    rounding step scales by a power of two); the FMA form re-centres the block
+    on a rounded mean, so it is held to the parity rule instead."""
+    say("u16 x2 scale", arith)
     p = synth.gen_random(4, (28, 27, 26), "u16", smooth=1.0)
     ref = (p.ref // 2).astype(np.uint16)
     flt = (p.flt // 2).astype(np.uint16)
+    ref2, flt2 = (ref * 2).astype(np.uint16), (flt * 2).astype(np.uint16)
     centers = gpu_select(ref, 5, 2, 0.4)
-    centers2 = gpu_select((ref * 2).astype(np.uint16), 5, 2, 0.4)
+    centers2 = gpu_select(ref2, 5, 2, 0.4)
     assert np.array_equal(centers, centers2)
-    d1, n1, _ = gpu_match(ref, flt, centers, 5, 4)
-    d2, n2, _ = gpu_match((ref * 2).astype(np.uint16), (flt * 2).astype(np.uint16), centers, 5, 4)
-    assert np.array_equal(d1, d2) and np.array_equal(n1, n2)
+    d1, n1, c1_ = gpu_match(ref, flt, centers, 5, 4)
+    d2, n2, c2_ = gpu_match(ref2, flt2, centers, 5, 4)
+    if arith == "dot2":
+        assert np.array_equal(d1, d2) and np.array_equal(n1, n2)
+    else:
+        check_match(ref, flt, centers, 5, 4, d1, n1, c1_, "x1")
+        check_match(ref2, flt2, centers, 5, 4, d2, n2, c2_, "x2")
 
 
 @pytest.mark.parametrize("dtype", ["u16", "f32"])
