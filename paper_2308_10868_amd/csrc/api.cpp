@@ -205,6 +205,9 @@ nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const in
     a.block = block;
     a.window = window;
     a.stats = workspace;
+    a.pairs = L.pair_off ? reinterpret_cast<const uint32_t *>(
+                               static_cast<const char *>(workspace) + L.pair_off)
+                         : nullptr;
     a.ox = L.ox;
     a.oy = L.oy;
     a.disp = disp;

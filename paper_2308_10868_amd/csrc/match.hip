@@ -65,6 +65,7 @@ struct Params {
     int w;
     int cz;  // displacement planes per z-chunk
     const void *stats;  // StatU16 / StatF32 records over block origins
+    const uint32_t *pv;  // plane-pair volume of flt (12-bit data)
     int ox, oy;
     int32_t *disp;
     float *ncc;
@@ -171,11 +172,10 @@ __device__ inline void write_result(const Params &p, int64_t blk, int dx, int dy
 // UNR chunks per lane are loaded before any is written so several global
 // loads are in flight, and the chunk coordinates advance incrementally (no
 // integer division in the loop).
-template <int NT, bool PAIR, typename Src, typename Make>
+template <int NT, bool PAIR, int UNR, typename Src, typename Make>
 __device__ inline void stage_planes(const Src *__restrict__ src, int nx, int ny, int x0, int y0,
                                     int z0, int ex, int ey, int ez, uint32_t *__restrict__ dst,
                                     int pitch, int plane, int py, int pz, Make make) {
-    constexpr int UNR = 4;
     const int cpr = (pitch + 3) >> 2;  // chunks per row
     const int total = pz * py * cpr;
     const int drow = NT / cpr, dxc = NT - drow * cpr;
@@ -227,6 +227,53 @@ __device__ inline void stage_planes(const Src *__restrict__ src, int nx, int ny,
     }
 }
 
+// Stage planes [z0, z0 + pz) of the window from the plane-pair volume as
+// plain copies into LDS at z*plane + y*pitch + x, with `pitch` and `plane`
+// multiples of 4 words.  Each lane moves whole 16-byte row chunks (one
+// global and one LDS access each); rows at or past `ey` re-read row ey-1 and
+// columns past the window's own width read whatever follows in the volume
+// row (the pair volume carries slack at its end), so no load needs a
+// predicate.  Those extra words only feed displacements that are masked out.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int NT, int UNR>
+__device__ inline void stage_rows(const uint32_t *__restrict__ src, int nx, int ny, int x0, int y0,
+                                  int z0, int ey, uint32_t *__restrict__ dst, int pitch,
+                                  int plane, int py, int pz) {
+    const int cpr = pitch >> 2;  // chunks per row
+    const int total = pz * py * cpr;
+    const int drow = NT / cpr, dxc = NT - drow * cpr;
+    int row = (int)threadIdx.x / cpr;
+    int xc = (int)threadIdx.x - row * cpr;
+    int z = row / py, y = row - z * py;
+    for (int c0 = 0; c0 < total; c0 += NT * UNR) {
+        u32x4 v[UNR];
+        int off[UNR];
+        bool live[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            live[u] = c0 + u * NT + (int)threadIdx.x < total;
+            const int zz = live[u] ? z : 0, yy = min(y, ey - 1);
+            const uint32_t *s = src + ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + (x0 + 4 * xc);
+            v[u] = *reinterpret_cast<const u32x4 *>(s);
+            off[u] = z * plane + y * pitch + 4 * xc;
+            xc += dxc;
+            y += drow;
+            if (xc >= cpr) {
+                xc -= cpr;
+                ++y;
+            }
+            while (y >= py) {
+                y -= py;
+                ++z;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (live[u]) *reinterpret_cast<u32x4 *>(dst + off[u]) = v[u];
+    }
+}
+
 // Exact int32 grouping for DOT2: a plane contributes at most B*B*2048*2048.
 template <int B>
 struct Groups {
@@ -265,6 +312,8 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     const Vox *flt = static_cast<const Vox *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
     const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1;
+    // LDS row pitch: DOT2 rows are whole 16-byte chunks
+    const int pitch = ARITH == DOT2 ? (PX + 3) & ~3 : PX;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1;
     auto tval = [&](int o) {
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
@@ -272,17 +321,15 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     };
 
     // ---- block statistics and the staged T table
-    const int plane = PY * PX + ZPAD;  // one pad dword per plane spreads LDS banks
+    // FMA: one pad dword per plane spreads LDS banks; DOT2 planes stay 16-byte
+    // aligned (pitch/4 odd or not, the dz-fastest lane order spreads them)
+    const int plane = PY * pitch + (ARITH == DOT2 ? 0 : ZPAD);
     auto stage_chunk = [&](int zc0, int ezc, float c) {
-        if constexpr (ARITH == DOT2)
-            stage_planes<NT, true>(flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win,
-                                   PX, plane, PY, ezc, [](Vox a, Vox b, bool nb) {
-                                       const int hi = nb ? (int)b - 2048 : 0;
-                                       return (uint32_t)(uint16_t)((int)a - 2048) |
-                                              ((uint32_t)(uint16_t)hi << 16);
-                                   });
+        if constexpr (ARITH == DOT2)  // plain copies of the precomputed pair words
+            stage_rows<NT, 4>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ey, win, pitch, plane,
+                              PY, ezc);
         else
-            stage_planes<NT, false>(
+            stage_planes<NT, false, 4>(
                 flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win, PX, plane, PY, ezc,
                 [c](Vox a, Vox, bool) { return __float_as_uint((float)a - c); });
     };
@@ -371,25 +418,30 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
             // the plane padding this spreads a wavefront's reads over the banks
             const int dzl = t % czn, tx = (t / czn) % txn, ty = t / (czn * txn);
             const int dz = zc0 + dzl;
-            const uint32_t *base = win + dzl * plane + ty * RY * PX + tx * RX;
+            const uint32_t *base = win + dzl * plane + ty * RY * pitch + tx * RX;
             // the tile's table records: all loaded at once (coordinates clamped
             // into the valid range, so every load is in bounds), either before
             // the multiply loop (PF: their latency hides behind it) or after
             using Rec = typename std::conditional<U16, StatU16, StatF32>::type;
             const Rec *table = static_cast<const Rec *>(p.stats);
             Rec rec[RX][RY];
-            const int64_t zrow = (int64_t)(g.wz0 + dz) * p.oy;
+            // records of displacements past the valid range read neighbouring
+            // origins (or the table's slack past its end); they are masked out
+            const Rec *rb = table + ((int64_t)(g.wz0 + dz) * p.oy + (g.wy0 + ty * RY)) * p.ox +
+                            (g.wx0 + tx * RX);
             auto load_recs = [&]() {
 #pragma unroll
                 for (int j = 0; j < RY; ++j)
 #pragma unroll
-                    for (int i = 0; i < RX; ++i) {
-                        const int xx = min(tx * RX + i, g.dx - 1), yy = min(ty * RY + j, g.dy - 1);
-                        rec[i][j] = table[(zrow + (g.wy0 + yy)) * p.ox + (g.wx0 + xx)];
-                    }
+                    for (int i = 0; i < RX; ++i) rec[i][j] = rb[j * p.ox + i];
             };
             if constexpr (PF) load_recs();
-            double xacc[RX][RY];  // cross term of each displacement of the tile
+            // cross term of each displacement of the tile, kept in the narrowest
+            // exact type (converted to FP64 per displacement in the ranking)
+            using XT = typename std::conditional<
+                ARITH == DOT2, typename std::conditional<NG == 1, int, double>::type,
+                float>::type;
+            XT xacc[RX][RY];
             if constexpr (ARITH == DOT2) {
                 int acc[RX][RY], acc0[RX][RY];
                 double dacc[NG > 2 ? RX : 1][NG > 2 ? RY : 1];
@@ -407,7 +459,8 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
 #pragma unroll
                     for (int oy = 0; oy < B; ++oy)
 #pragma unroll
-                        for (int ox = 0; ox < B; ++ox) tq[oy][ox] = (int)tpm[oy * BP + ox];
+                        for (int ox = 0; ox < B; ++ox)  // uniform: kept in scalar registers
+                            tq[oy][ox] = __builtin_amdgcn_readfirstlane((int)tpm[oy * BP + ox]);
                     const lds_word *wm = (const lds_word *)(base + 2 * m * plane);
                     // rows are software-pipelined: row yw+1 is read while row yw
                     // is multiplied
@@ -419,7 +472,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                         if (yw + 1 < RY + B - 1) {
 #pragma unroll
                             for (int xw = 0; xw < RX + B - 1; ++xw)
-                                fr[(yw + 1) & 1][xw] = (int)wm[(yw + 1) * PX + xw];
+                                fr[(yw + 1) & 1][xw] = (int)wm[(yw + 1) * pitch + xw];
                         }
                         const int *f = fr[yw & 1];
 #pragma unroll
@@ -463,7 +516,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
 #pragma unroll
                     for (int j = 0; j < RY; ++j) {
                         if constexpr (NG == 1)
-                            xacc[i][j] = (double)acc[i][j];
+                            xacc[i][j] = acc[i][j];
                         else if constexpr (NG == 2)
                             xacc[i][j] = (double)acc0[i][j] + (double)acc[i][j];
                         else
@@ -492,7 +545,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                         if (yw + 1 < RY + B - 1) {
 #pragma unroll
                             for (int xw = 0; xw < RX + B - 1; ++xw)
-                                fr[(yw + 1) & 1][xw] = __uint_as_float(wz[(yw + 1) * PX + xw]);
+                                fr[(yw + 1) & 1][xw] = __uint_as_float(wz[(yw + 1) * pitch + xw]);
                         }
                         const float *f = fr[yw & 1];
 #pragma unroll
@@ -510,7 +563,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
 #pragma unroll
                 for (int i = 0; i < RX; ++i)
 #pragma unroll
-                    for (int j = 0; j < RY; ++j) xacc[i][j] = (double)acc[i][j];
+                    for (int j = 0; j < RY; ++j) xacc[i][j] = acc[i][j];
             }
             // ---- rank the tile's displacements: key = N*cov * rsqrt(N*varF);
             // invalid displacements are masked, no branch per displacement
@@ -530,10 +583,11 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                     KeyT key;
                     if constexpr (U16) {
                         const double cov =
-                            __builtin_fma(dN, xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
+                            __builtin_fma(dN, (double)xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
                         key = (float)cov * rec[i][j].r;
                     } else {
-                        const double cov = dN * xacc[i][j] - sTc * (rec[i][j].s - dN * (double)c);
+                        const double cov =
+                            dN * (double)xacc[i][j] - sTc * (rec[i][j].s - dN * (double)c);
                         key = cov * rec[i][j].r;
                     }
                     const bool take = valid && key > tk;  // ties keep the smaller index
@@ -557,19 +611,40 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                    (g.cx - H + ddx + ox)];
     };
     if constexpr (U16) {
-        // the exact sums of T and T^2 are already known (st); F and TF here
-        long long sums[3] = {0, 0, 0};  // F, F^2, TF (raw 12-bit values)
-        for (int o = tid; o < N; o += NT) {
-            const long long tv = tval(o), fv = fval(o);
-            sums[0] += fv;
-            sums[1] += fv * fv;
-            sums[2] += tv * fv;
+        // the exact sums of T and T^2 are already known (st); F and TF here.
+        // Sums of shifted values (F - 2048, T - 2048) give the same covariance
+        // and spreads as the raw values, and st is shift-free.
+        long long sums[3] = {0, 0, 0};  // F, F^2, TF
+        long long tS = st[0];             // sum of T in the same offset frame
+        if (ARITH == DOT2 && g.dz <= p.cz) {
+            // single chunk: the winner's window and the T table are both in LDS,
+            // as int16 values offset by -2048
+            tS = st[0] - 2048ll * N;
+            const int zr = ddz - g.loz, yr = ddy - g.loy, xr = ddx - g.lox;
+            for (int i = tid; i < P * B * B; i += NT) {
+                const int m = i / (B * B), oy = (i / B) % B, ox = i % B;
+                const uint32_t tw = tp[(m * B + oy) * BP + ox];
+                const uint32_t fw = win[(zr + 2 * m) * plane + (yr + oy) * pitch + (xr + ox)];
+                const long long tlo = (short)(tw & 0xffff), thi = (short)(tw >> 16);
+                const long long flo = (short)(fw & 0xffff);
+                const long long fhi = 2 * m + 1 < B ? (long long)(short)(fw >> 16) : 0;
+                sums[0] += flo + fhi;
+                sums[1] += flo * flo + fhi * fhi;
+                sums[2] += tlo * flo + thi * fhi;
+            }
+        } else {
+            for (int o = tid; o < N; o += NT) {
+                const long long tv = tval(o), fv = fval(o);
+                sums[0] += fv;
+                sums[1] += fv * fv;
+                sums[2] += tv * fv;
+            }
         }
         wg_sum<NT, long long, 3>(sums, s_red);
         if (tid == 0) {
             const long long vt = (long long)N * st[1] - st[0] * st[0];
             const long long vf = (long long)N * sums[1] - sums[0] * sums[0];
-            const long long cv = (long long)N * sums[2] - st[0] * sums[0];
+            const long long cv = (long long)N * sums[2] - tS * sums[0];
             const double v = (vt > 0 && vf > 0) ? (double)cv / sqrt((double)vt * (double)vf) : 0.0;
             write_result(p, blk, ddx, ddy, ddz, (float)v);
         }
@@ -641,6 +716,7 @@ size_t window_plane_bytes(const Variant &v, int w) {
     const int d = 2 * w + 1;
     const int px = (d + v.rx - 1) / v.rx * v.rx + v.b - 1;
     const int py = (d + v.ry - 1) / v.ry * v.ry + v.b - 1;
+    if (v.arith == DOT2) return (size_t)((px + 3) & ~3) * py * 4;
     return ((size_t)px * py + ZPAD) * 4;
 }
 
@@ -781,6 +857,7 @@ hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream)
     p.w = a.window;
     p.cz = pl.cz;
     p.stats = a.stats;
+    p.pv = a.pairs;
     p.ox = a.ox;
     p.oy = a.oy;
     p.disp = a.disp;

@@ -41,8 +41,13 @@ struct StatF32 {
     double s;
     double r;
 };
+// 12-bit volumes also get a plane-pair copy of `flt` for the dot2 search:
+// pairs[z][y][x] = (F(z) - 2048) | (F(z+1) - 2048) << 16 as two int16 halves
+// (upper half 0 on the last plane), 4 bytes per voxel at byte `pair_off`.
+constexpr int kTileSlack = 16;  // >= the largest search tile edge
 struct StatsLayout {
     size_t total;
+    size_t pair_off;  // 0: no pair volume (float data)
     int32_t ox, oy, oz;
 };
 StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
@@ -59,6 +64,7 @@ struct MatchArgs {
     int64_t n;
     int32_t block, window;
     const void *stats;   // StatU16 or StatF32 records, [oz][oy][ox]
+    const uint32_t *pairs;  // plane-pair volume (12-bit data), else nullptr
     int32_t ox, oy;      // origin-grid extents (x, y) of the stats arrays
     int32_t *disp;
     float *ncc;

@@ -185,6 +185,31 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
         });
 }
 
+// Plane-pair copy of a 12-bit volume: one 4-byte word per voxel holding the
+// voxel and the one a plane above, both offset by -2048 into int16 (the next
+// plane's half is 0 on the last plane).  Four consecutive voxels per thread.
+__global__ __launch_bounds__(256) void k_pair_volume(const uint16_t *__restrict__ flt,
+                                                     int64_t nvox, int64_t pstride,
+                                                     uint32_t *__restrict__ out) {
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (i >= nvox) return;
+    auto word = [&](int64_t j) {
+        const uint32_t lo = (uint16_t)((int)flt[j] - 2048);
+        const uint32_t hi = j + pstride < nvox ? (uint16_t)((int)flt[j + pstride] - 2048) : 0u;
+        return lo | hi << 16;
+    };
+    if (i + 4 <= nvox) {
+        uint4 w;
+        w.x = word(i);
+        w.y = word(i + 1);
+        w.z = word(i + 2);
+        w.w = word(i + 3);
+        *reinterpret_cast<uint4 *>(out + i) = w;
+    } else {
+        for (int64_t j = i; j < nvox; ++j) out[j] = word(j);
+    }
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
@@ -194,8 +219,15 @@ StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block) 
     L.ox = dims[0] - block + 1;
     L.oy = dims[1] - block + 1;
     L.oz = dims[2] - block + 1;
-    const size_t nvox = (size_t)L.ox * L.oy * L.oz;
+    // slack after the table: the search reads whole tiles of records, up to
+    // kTileSlack rows and columns past the last valid origin
+    const size_t nvox = (size_t)L.ox * L.oy * L.oz + (size_t)kTileSlack * (L.ox + 1);
     L.total = align_up(nvox * (dtype == NRR_U16 ? sizeof(StatU16) : sizeof(StatF32)), 256);
+    L.pair_off = 0;
+    if (dtype == NRR_U16) {  // + slack: staging reads whole 4-word row chunks
+        L.pair_off = L.total;
+        L.total += align_up(((size_t)dims[0] * dims[1] * dims[2] + 64) * 4, 256);
+    }
     return L;
 }
 
@@ -204,11 +236,16 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     StatsLayout L = stats_layout(dtype, dims, block);
     char *ws = static_cast<char *>(workspace);
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + ZC - 1) / ZC);
-    if (dtype == NRR_U16)
+    if (dtype == NRR_U16) {
         hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)block * 256 * 8, stream,
                            static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], block,
                            L.ox, L.oy, L.oz, reinterpret_cast<StatU16 *>(ws));
-    else
+        const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+        const int64_t groups = (nvox + 1023) / 1024;
+        hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(flt), nvox, (int64_t)dims[0] * dims[1],
+                           reinterpret_cast<uint32_t *>(ws + L.pair_off));
+    } else
         hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)block * 256 * 16, stream,
                            static_cast<const float *>(flt), dims[0], dims[1], dims[2], block,
                            L.ox, L.oy, L.oz, reinterpret_cast<StatF32 *>(ws));
