@@ -229,34 +229,39 @@ __device__ inline void stage_planes(const Src *__restrict__ src, int nx, int ny,
 
 // Stage planes [z0, z0 + pz) of the window from the plane-pair volume as
 // plain copies into LDS at z*plane + y*pitch + x, with `pitch` and `plane`
-// multiples of 4 words.  Each lane moves whole 16-byte row chunks (one
+// multiples of CW words.  Each lane moves whole CW-word row chunks (one
 // global and one LDS access each); rows at or past `ey` re-read row ey-1 and
 // columns past the window's own width read whatever follows in the volume
 // row (the pair volume carries slack at its end), so no load needs a
 // predicate.  Those extra words only feed displacements that are masked out.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4), aligned(4)));
+template <int CW>
+struct Chunk {
+    typedef uint32_t type __attribute__((ext_vector_type(CW), aligned(4)));
+};
+constexpr int CW = 4;  // row chunk width of the DOT2 window (16-byte copies)
 
 template <int NT, int UNR>
 __device__ inline void stage_rows(const uint32_t *__restrict__ src, int nx, int ny, int x0, int y0,
                                   int z0, int ey, uint32_t *__restrict__ dst, int pitch,
                                   int plane, int py, int pz) {
-    const int cpr = pitch >> 2;  // chunks per row
+    using V = typename Chunk<CW>::type;
+    const int cpr = pitch / CW;  // chunks per row
     const int total = pz * py * cpr;
     const int drow = NT / cpr, dxc = NT - drow * cpr;
     int row = (int)threadIdx.x / cpr;
     int xc = (int)threadIdx.x - row * cpr;
     int z = row / py, y = row - z * py;
     for (int c0 = 0; c0 < total; c0 += NT * UNR) {
-        u32x4 v[UNR];
+        V v[UNR];
         int off[UNR];
         bool live[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
             live[u] = c0 + u * NT + (int)threadIdx.x < total;
             const int zz = live[u] ? z : 0, yy = min(y, ey - 1);
-            const uint32_t *s = src + ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + (x0 + 4 * xc);
-            v[u] = *reinterpret_cast<const u32x4 *>(s);
-            off[u] = z * plane + y * pitch + 4 * xc;
+            const uint32_t *s = src + ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx + (x0 + CW * xc);
+            v[u] = *reinterpret_cast<const V *>(s);
+            off[u] = z * plane + y * pitch + CW * xc;
             xc += dxc;
             y += drow;
             if (xc >= cpr) {
@@ -270,7 +275,7 @@ __device__ inline void stage_rows(const uint32_t *__restrict__ src, int nx, int 
         }
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (live[u]) *reinterpret_cast<u32x4 *>(dst + off[u]) = v[u];
+            if (live[u]) *reinterpret_cast<V *>(dst + off[u]) = v[u];
     }
 }
 
@@ -283,6 +288,129 @@ struct Groups {
     static constexpr int NG = (P + GPAIRS - 1) / GPAIRS;
     static_assert(GPAIRS >= 1, "block edge too large for exact int32 groups");
 };
+
+// DOT2 cross terms X(d) = sum_o T'(o) F'(o + d) of an RX x RY tile of
+// displacements at one dz: `tp` is the block's pair table [P][B][BP], `base`
+// the tile's first window row and column, and the window plane of pair m is
+// in ring slot (slot + 2m) mod R.  Exact: int32 groups of plane pairs that
+// cannot overflow, combined in FP64 when a block needs more than one.
+template <int B, int RX, int RY, typename XT>
+__device__ __attribute__((always_inline)) inline void dot2_cross(
+    const uint32_t *tp, const uint32_t *base, int slot, int R, int plane, int pitch,
+    XT (&xacc)[RX][RY]) {
+    constexpr int P = Groups<B>::P, GP = Groups<B>::GPAIRS, NG = Groups<B>::NG;
+    constexpr int BP = (B + 3) & ~3;
+    int acc[RX][RY], acc0[RX][RY];
+    double dacc[NG > 2 ? RX : 1][NG > 2 ? RY : 1];
+#pragma unroll
+    for (int i = 0; i < RX; ++i)
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            acc[i][j] = 0;
+            acc0[i][j] = 0;
+            if constexpr (NG > 2) dacc[i][j] = 0.0;
+        }
+    for (int m = 0; m < P; ++m) {
+        int tq[B][B];
+        const uint32_t *tpm = tp + m * B * BP;
+#pragma unroll
+        for (int oy = 0; oy < B; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < B; ++ox)  // uniform: kept in scalar registers
+                tq[oy][ox] = __builtin_amdgcn_readfirstlane((int)tpm[oy * BP + ox]);
+        const lds_word *wm = (const lds_word *)(base + slot * plane);
+        slot += 2;
+        if (slot >= R) slot -= R;
+        // rows are software-pipelined: row yw+1 is read while row yw
+        // is multiplied
+        int fr[2][RX + B - 1];
+#pragma unroll
+        for (int xw = 0; xw < RX + B - 1; ++xw) fr[0][xw] = (int)wm[xw];
+#pragma unroll
+        for (int yw = 0; yw < RY + B - 1; ++yw) {
+            if (yw + 1 < RY + B - 1) {
+#pragma unroll
+                for (int xw = 0; xw < RX + B - 1; ++xw)
+                    fr[(yw + 1) & 1][xw] = (int)wm[(yw + 1) * pitch + xw];
+            }
+            const int *f = fr[yw & 1];
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                const int oy = yw - j;
+                if (oy < 0 || oy >= B) continue;
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int ox = 0; ox < B; ++ox)
+                        acc[i][j] = __builtin_amdgcn_sdot2(
+                            __builtin_bit_cast(short2v, f[i + ox]),
+                            __builtin_bit_cast(short2v, tq[oy][ox]), acc[i][j],
+                            false);
+            }
+        }
+        if constexpr (NG == 2) {
+            if (m == GP - 1) {
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        acc0[i][j] = acc[i][j];
+                        acc[i][j] = 0;
+                    }
+            }
+        } else if constexpr (NG > 2) {
+            if ((m + 1) % GP == 0) {
+#pragma unroll
+                for (int i = 0; i < RX; ++i)
+#pragma unroll
+                    for (int j = 0; j < RY; ++j) {
+                        dacc[i][j] += (double)acc[i][j];
+                        acc[i][j] = 0;
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RX; ++i)
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            if constexpr (NG == 1)
+                xacc[i][j] = acc[i][j];
+            else if constexpr (NG == 2)
+                xacc[i][j] = (double)acc0[i][j] + (double)acc[i][j];
+            else
+                xacc[i][j] = dacc[i][j] + (double)acc[i][j];
+        }
+}
+
+// Ranking of a tile: key = N*cov * rsqrt(N*varF), proportional to the NCC for
+// the block at hand; keeps the largest key and, among equal keys, the
+// smallest shift index (irow + j*side + i).  Displacements past the valid
+// extents (nvx, nvy) are masked without a branch.  For 12-bit data the staged
+// F sums are offset by `fshift` from the table's.
+template <bool U16, int RX, int RY, typename Rec, typename XT, typename KeyT>
+__device__ __attribute__((always_inline)) inline void rank_tile(
+    const Rec (&rec)[RX][RY], const XT (&xacc)[RX][RY], double dN, double tsum, double fshift,
+    float c, int nvx, int nvy, int irow, int side, KeyT &tk, int &ti) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int i = 0; i < RX; ++i) {  // increasing shift index
+            const bool valid = i < nvx && j < nvy;
+            KeyT key;
+            if constexpr (U16) {
+                const double cov =
+                    __builtin_fma(dN, (double)xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
+                key = (float)cov * rec[i][j].r;
+            } else {
+                const double cov = dN * (double)xacc[i][j] - tsum * (rec[i][j].s - dN * (double)c);
+                key = cov * rec[i][j].r;
+            }
+            const bool take = valid && key > tk;  // ties keep the smaller index
+            tk = take ? key : tk;
+            ti = take ? irow + j * side + i : ti;
+        }
+}
 
 template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
 __global__ __launch_bounds__(NT) void k_match(Params p) {
@@ -312,8 +440,8 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     const Vox *flt = static_cast<const Vox *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
     const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1;
-    // LDS row pitch: DOT2 rows are whole 16-byte chunks
-    const int pitch = ARITH == DOT2 ? (PX + 3) & ~3 : PX;
+    // LDS row pitch: DOT2 rows are whole CW-word chunks
+    const int pitch = ARITH == DOT2 ? (PX + CW - 1) / CW * CW : PX;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1;
     auto tval = [&](int o) {
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
@@ -321,13 +449,13 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     };
 
     // ---- block statistics and the staged T table
-    // FMA: one pad dword per plane spreads LDS banks; DOT2 planes stay 16-byte
-    // aligned (pitch/4 odd or not, the dz-fastest lane order spreads them)
+    // FMA: one pad dword per plane spreads LDS banks; DOT2 planes stay whole
+    // row chunks (the dz-fastest lane order spreads their banks)
     const int plane = PY * pitch + (ARITH == DOT2 ? 0 : ZPAD);
     auto stage_chunk = [&](int zc0, int ezc, float c) {
         if constexpr (ARITH == DOT2)  // plain copies of the precomputed pair words
-            stage_rows<NT, 4>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ey, win, pitch, plane,
-                              PY, ezc);
+            stage_rows<NT, 8>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ey, win, pitch,
+                                  plane, PY, ezc);
         else
             stage_planes<NT, false, 4>(
                 flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win, PX, plane, PY, ezc,
@@ -404,12 +532,27 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     const int side = 2 * p.w + 1;
     KeyT bk = -INFINITY;
     int bi = INT_MAX;
+    // DOT2 keeps the staged planes in a ring of R plane slots (window plane q
+    // in slot q mod R), so a later chunk stages only the planes it adds
+    const int R = min(p.cz, g.dz) + B - 1;
+    int staged = R;  // window planes [0, staged) staged so far (chunk 0 above)
     for (int zc0 = 0; zc0 < g.dz; zc0 += p.cz) {
         const int czn = min(p.cz, g.dz - zc0);  // displacement planes in this chunk
         const int ezc = czn + B - 1;            // window planes in this chunk
         if (zc0 > 0) {                          // the first chunk was staged above
             __syncthreads();                    // previous chunk fully consumed
-            stage_chunk(zc0, ezc, c);
+            if constexpr (ARITH == DOT2) {
+                // new planes [staged, zc0 + ezc) replace planes below zc0
+                for (int q = staged; q < zc0 + ezc;) {
+                    const int slot = q % R, n = min(zc0 + ezc - q, R - slot);
+                    stage_rows<NT, 8>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + q, ey,
+                                          win + slot * plane, pitch, plane, PY, n);
+                    q += n;
+                }
+                staged = zc0 + ezc;
+            } else {
+                stage_chunk(zc0, ezc, c);
+            }
             __syncthreads();
         }
         const int ntiles = txn * tyn * czn;
@@ -418,7 +561,8 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
             // the plane padding this spreads a wavefront's reads over the banks
             const int dzl = t % czn, tx = (t / czn) % txn, ty = t / (czn * txn);
             const int dz = zc0 + dzl;
-            const uint32_t *base = win + dzl * plane + ty * RY * pitch + tx * RX;
+            const uint32_t *base =
+                win + (ARITH == DOT2 ? 0 : dzl * plane) + ty * RY * pitch + tx * RX;
             // the tile's table records: all loaded at once (coordinates clamped
             // into the valid range, so every load is in bounds), either before
             // the multiply loop (PF: their latency hides behind it) or after
@@ -443,85 +587,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                 float>::type;
             XT xacc[RX][RY];
             if constexpr (ARITH == DOT2) {
-                int acc[RX][RY], acc0[RX][RY];
-                double dacc[NG > 2 ? RX : 1][NG > 2 ? RY : 1];
-#pragma unroll
-                for (int i = 0; i < RX; ++i)
-#pragma unroll
-                    for (int j = 0; j < RY; ++j) {
-                        acc[i][j] = 0;
-                        acc0[i][j] = 0;
-                        if constexpr (NG > 2) dacc[i][j] = 0.0;
-                    }
-                for (int m = 0; m < P; ++m) {
-                    int tq[B][B];
-                    const uint32_t *tpm = tp + m * B * BP;
-#pragma unroll
-                    for (int oy = 0; oy < B; ++oy)
-#pragma unroll
-                        for (int ox = 0; ox < B; ++ox)  // uniform: kept in scalar registers
-                            tq[oy][ox] = __builtin_amdgcn_readfirstlane((int)tpm[oy * BP + ox]);
-                    const lds_word *wm = (const lds_word *)(base + 2 * m * plane);
-                    // rows are software-pipelined: row yw+1 is read while row yw
-                    // is multiplied
-                    int fr[2][RX + B - 1];
-#pragma unroll
-                    for (int xw = 0; xw < RX + B - 1; ++xw) fr[0][xw] = (int)wm[xw];
-#pragma unroll
-                    for (int yw = 0; yw < RY + B - 1; ++yw) {
-                        if (yw + 1 < RY + B - 1) {
-#pragma unroll
-                            for (int xw = 0; xw < RX + B - 1; ++xw)
-                                fr[(yw + 1) & 1][xw] = (int)wm[(yw + 1) * pitch + xw];
-                        }
-                        const int *f = fr[yw & 1];
-#pragma unroll
-                        for (int j = 0; j < RY; ++j) {
-                            const int oy = yw - j;
-                            if (oy < 0 || oy >= B) continue;
-#pragma unroll
-                            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                                for (int ox = 0; ox < B; ++ox)
-                                    acc[i][j] = __builtin_amdgcn_sdot2(
-                                        __builtin_bit_cast(short2v, f[i + ox]),
-                                        __builtin_bit_cast(short2v, tq[oy][ox]), acc[i][j],
-                                        false);
-                        }
-                    }
-                    if constexpr (NG == 2) {
-                        if (m == GP - 1) {
-#pragma unroll
-                            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                                for (int j = 0; j < RY; ++j) {
-                                    acc0[i][j] = acc[i][j];
-                                    acc[i][j] = 0;
-                                }
-                        }
-                    } else if constexpr (NG > 2) {
-                        if ((m + 1) % GP == 0) {
-#pragma unroll
-                            for (int i = 0; i < RX; ++i)
-#pragma unroll
-                                for (int j = 0; j < RY; ++j) {
-                                    dacc[i][j] += (double)acc[i][j];
-                                    acc[i][j] = 0;
-                                }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < RX; ++i)
-#pragma unroll
-                    for (int j = 0; j < RY; ++j) {
-                        if constexpr (NG == 1)
-                            xacc[i][j] = acc[i][j];
-                        else if constexpr (NG == 2)
-                            xacc[i][j] = (double)acc0[i][j] + (double)acc[i][j];
-                        else
-                            xacc[i][j] = dacc[i][j] + (double)acc[i][j];
-                    }
+                dot2_cross<B, RX, RY>(tp, base, (zc0 + dzl) % R, R, plane, pitch, xacc);
             } else {
                 float acc[RX][RY];
 #pragma unroll
@@ -572,28 +638,11 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                              (g.lox + tx * RX + p.w);
             // sum of the staged F: DOT2 F-2048 (= the table's s), FMA F-c
             const double fshift = ARITH == DOT2 ? 0.0 : dN * (2048.0 - (double)c);
-            const double tsum = ARITH == DOT2 ? (double)sT : sTc;
+            const double tsum = ARITH == DOT2 ? (double)sT : sTc;  // sum of the staged T
             KeyT tk = -INFINITY;
             int ti = INT_MAX;
-#pragma unroll
-            for (int j = 0; j < RY; ++j)
-#pragma unroll
-                for (int i = 0; i < RX; ++i) {  // increasing shift index
-                    const bool valid = tx * RX + i < g.dx && ty * RY + j < g.dy;
-                    KeyT key;
-                    if constexpr (U16) {
-                        const double cov =
-                            __builtin_fma(dN, (double)xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
-                        key = (float)cov * rec[i][j].r;
-                    } else {
-                        const double cov =
-                            dN * (double)xacc[i][j] - sTc * (rec[i][j].s - dN * (double)c);
-                        key = cov * rec[i][j].r;
-                    }
-                    const bool take = valid && key > tk;  // ties keep the smaller index
-                    tk = take ? key : tk;
-                    ti = take ? irow + j * side + i : ti;
-                }
+            rank_tile<U16>(rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX, g.dy - ty * RY, irow,
+                           side, tk, ti);
             better(bk, bi, tk, ti);
         }
     }
@@ -616,15 +665,21 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
         // and spreads as the raw values, and st is shift-free.
         long long sums[3] = {0, 0, 0};  // F, F^2, TF
         long long tS = st[0];             // sum of T in the same offset frame
-        if (ARITH == DOT2 && g.dz <= p.cz) {
-            // single chunk: the winner's window and the T table are both in LDS,
-            // as int16 values offset by -2048
+        if constexpr (ARITH == DOT2) {
+            // pair words of the winning window: from the LDS ring when its planes
+            // are still staged, else from the plane-pair volume; the block's own
+            // words are in the T table.  Values are int16, offset by -2048.
             tS = st[0] - 2048ll * N;
             const int zr = ddz - g.loz, yr = ddy - g.loy, xr = ddx - g.lox;
+            const bool in_lds = zr >= staged - R;
             for (int i = tid; i < P * B * B; i += NT) {
                 const int m = i / (B * B), oy = (i / B) % B, ox = i % B;
                 const uint32_t tw = tp[(m * B + oy) * BP + ox];
-                const uint32_t fw = win[(zr + 2 * m) * plane + (yr + oy) * pitch + (xr + ox)];
+                const int q = zr + 2 * m;
+                const uint32_t fw =
+                    in_lds ? win[(q % R) * plane + (yr + oy) * pitch + (xr + ox)]
+                           : p.pv[((int64_t)(g.wz0 + q) * p.ny + (g.wy0 + yr + oy)) * p.nx +
+                                  (g.wx0 + xr + ox)];
                 const long long tlo = (short)(tw & 0xffff), thi = (short)(tw >> 16);
                 const long long flo = (short)(fw & 0xffff);
                 const long long fhi = 2 * m + 1 < B ? (long long)(short)(fw >> 16) : 0;
@@ -669,6 +724,7 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     }
 }
 
+
 // ------------------------------------------------------------ dispatch
 
 typedef void (*kernel_t)(Params);
@@ -686,18 +742,19 @@ struct Variant {
 #define V32F(B, RX, RY, NT, PF) \
     {NRR_F32, FMA, B, RX, RY, NT, PF, k_match<float, FMA, B, RX, RY, NT, PF>}
 
+// Order matters only between equal-cost shapes (the first wins).
 const Variant kVariants[] = {
     V16D(3, 4, 4, 256, 0),  V16D(5, 4, 4, 256, 0),  V16D(5, 3, 7, 448, 0),
-    V16D(7, 4, 4, 256, 0),  V16D(7, 3, 7, 448, 0),  V16D(7, 3, 7, 256, 0),
-    V16D(7, 3, 7, 256, 1),  V16D(7, 3, 7, 448, 1),  V16D(7, 3, 5, 256, 0),
-    V16D(7, 5, 5, 256, 0),  V16D(9, 4, 4, 256, 0),  V16D(9, 5, 5, 256, 0),
-    V16D(11, 3, 3, 256, 0), V16D(13, 3, 3, 256, 0), V16D(15, 2, 2, 256, 0),
-    V16F(3, 4, 4, 256, 0),  V16F(5, 4, 4, 256, 0),  V16F(5, 3, 7, 448, 0),
-    V16F(7, 4, 4, 256, 0),  V16F(7, 3, 7, 448, 0),  V16F(9, 4, 4, 256, 0),
-    V16F(9, 5, 5, 256, 0),  V16F(11, 3, 3, 256, 0), V16F(13, 3, 3, 256, 0),
-    V16F(15, 2, 2, 256, 0), V32F(3, 4, 4, 256, 0),  V32F(5, 4, 4, 256, 0),
-    V32F(7, 4, 4, 256, 0),  V32F(7, 3, 7, 448, 0),  V32F(9, 4, 4, 256, 0),
-    V32F(11, 3, 3, 256, 0), V32F(13, 3, 3, 256, 0), V32F(15, 2, 2, 256, 0),
+    V16D(7, 3, 7, 256, 1),  V16D(7, 3, 7, 256, 0),  V16D(7, 4, 4, 256, 0),
+    V16D(7, 3, 5, 256, 0),  V16D(7, 5, 5, 256, 0),  V16D(9, 4, 4, 256, 0),
+    V16D(9, 5, 5, 256, 0),  V16D(11, 3, 3, 256, 0), V16D(13, 3, 3, 256, 0),
+    V16D(15, 2, 2, 256, 0), V16F(3, 4, 4, 256, 0),  V16F(5, 4, 4, 256, 0),
+    V16F(5, 3, 7, 448, 0),  V16F(7, 4, 4, 256, 0),  V16F(7, 3, 7, 448, 0),
+    V16F(9, 4, 4, 256, 0),  V16F(9, 5, 5, 256, 0),  V16F(11, 3, 3, 256, 0),
+    V16F(13, 3, 3, 256, 0), V16F(15, 2, 2, 256, 0), V32F(3, 4, 4, 256, 0),
+    V32F(5, 4, 4, 256, 0),  V32F(7, 4, 4, 256, 0),  V32F(7, 3, 7, 448, 0),
+    V32F(9, 4, 4, 256, 0),  V32F(11, 3, 3, 256, 0), V32F(13, 3, 3, 256, 0),
+    V32F(15, 2, 2, 256, 0),
 };
 
 struct Plan {
@@ -716,7 +773,9 @@ size_t window_plane_bytes(const Variant &v, int w) {
     const int d = 2 * w + 1;
     const int px = (d + v.rx - 1) / v.rx * v.rx + v.b - 1;
     const int py = (d + v.ry - 1) / v.ry * v.ry + v.b - 1;
-    if (v.arith == DOT2) return (size_t)((px + 3) & ~3) * py * 4;
+    if (v.arith == DOT2) {
+        return (size_t)((px + CW - 1) / CW * CW) * py * 4;
+    }
     return ((size_t)px * py + ZPAD) * 4;
 }
 
