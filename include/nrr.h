@@ -158,6 +158,93 @@ nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype 
                                     float *conf, const void *workspace, size_t workspace_bytes,
                                     void *stream);
 
+/* ------------------------------------------------------------------ tuning
+ * Tile-shape autotuner.  The exhaustive search can run with several compiled
+ * shapes (displacement tile per thread, threads per workgroup, prefetch of
+ * the statistics records, number of displacement planes staged at once);
+ * which is fastest depends on block, window and device.  The paper tunes
+ * its GPU launch configuration by hand (its GPU timing discussion reports a
+ * large gain from it); here the library times every shape it has for
+ * (dtype, block, window) on the caller's own data and keeps the fastest for
+ * every later search in this process with that (dtype, block, window):
+ * nrr_block_match, nrr_block_match_prepared and the batched search.
+ *
+ *  A shape: arith 0 = dot2 (12-bit data), 1 = FMA; rx x ry displacements
+ *  per thread; nt threads; pf 1 = records prefetched; cz displacement planes
+ *  staged at once (0 in requests: as planned).
+ *
+ * nrr_tune_match takes the arguments of nrr_block_match_prepared (workspace
+ * prepared by nrr_window_stats); the outputs hold the results of the last
+ * trial (every shape computes the same results).  reps >= 1 timed launches
+ * per shape after one warm-up.  It synchronises `stream`.  best (host,
+ * optional) receives the chosen shape, best_us (host, optional) its mean
+ * time in microseconds.  Errors as nrr_block_match_prepared, INVALID_ARG for
+ * reps < 1. */
+typedef struct {
+    int32_t arith, rx, ry, nt, pf, cz;
+} nrr_tile_shape;
+
+nrr_status nrr_tune_match(const void *ref, const void *flt, nrr_dtype dtype,
+                          const int32_t dims[3], const int32_t *centers, int64_t n, int32_t block,
+                          int32_t window, int32_t *disp, float *ncc, float *conf,
+                          const void *workspace, size_t workspace_bytes, int32_t reps,
+                          nrr_tile_shape *best, double *best_us, void *stream);
+
+/* The tuned shape for (dtype, block, window) (UNSUPPORTED if none yet), and
+ * forgetting every tuned shape.  Host only. */
+nrr_status nrr_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, nrr_tile_shape *out);
+nrr_status nrr_clear_tuning(void);
+
+/* ----------------------------------------------------------- batched search
+ * The paper's intra-operative parametric search (block size, window and
+ * selection fraction varied over one registration) as one batch: S
+ * parameter sets over one volume pair, each a variance-ranked selection
+ * (nrr_select_blocks with that set's block, stride and fraction) followed by
+ * the exhaustive search of every selected block (nrr_block_match with that
+ * set's window).  Results are identical to those S pairs of calls.
+ *
+ * The batch runs as one selection launch (a workgroup per set; each set's
+ * candidate grid must have at most 4096 blocks), the window statistics of
+ * each distinct block size, and ONE persistent search launch over the blocks
+ * of every set (the sets of largest cost first, the tile shape of each set
+ * from the tuned table or the cost model).  With use_graph the launches are
+ * captured once into a HIP graph and each run replays it.
+ *
+ * nrr_batch_layout (host only): offsets[0..nsets] - set s owns output rows
+ * offsets[s] .. offsets[s+1]-1 (K_s rows, in the order of `sets`) - and the
+ * device workspace bytes of the plan.  Errors: INVALID_ARG (a malformed set:
+ * rules of nrr_select_blocks and nrr_block_match), UNSUPPORTED (candidate
+ * grid above 4096 blocks, or no compiled shape for a set).
+ *
+ * nrr_batch_plan_create: ref/flt device volumes; centers/disp int32
+ * [rows][3], ncc/conf float [rows] device outputs; workspace device bytes as
+ * nrr_batch_layout says.  All pointers stay owned by the caller and must
+ * outlive the plan; every run rewrites the outputs and the workspace.  The
+ * set tables are copied into the workspace during creation (synchronous).
+ * *plan receives a host object released by nrr_batch_plan_destroy.
+ *
+ * nrr_batch_plan_run enqueues one batch on `stream` (asynchronous; a graph
+ * launch when the plan holds one).  Runs of one plan must not overlap. */
+typedef struct {
+    int32_t block, window, stride;
+    double fraction;
+} nrr_param_set;
+
+typedef struct nrr_batch_plan nrr_batch_plan;
+
+nrr_status nrr_batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
+                            int32_t nsets, int64_t *offsets, size_t *workspace_bytes);
+
+nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dtype,
+                                 const int32_t dims[3], const nrr_param_set *sets, int32_t nsets,
+                                 int32_t *centers, int32_t *disp, float *ncc, float *conf,
+                                 void *workspace, size_t workspace_bytes, int32_t use_graph,
+                                 void *stream, nrr_batch_plan **plan);
+
+nrr_status nrr_batch_plan_run(nrr_batch_plan *plan, void *stream);
+
+nrr_status nrr_batch_plan_destroy(nrr_batch_plan *plan);
+
 /* ------------------------------------------------------------- diagnostics */
 
 /* Static string for a status code. */

@@ -31,6 +31,12 @@ __all__ = [
     "select_blocks",
     "block_match",
     "window_stats",
+    "tune_match",
+    "tuned_shape",
+    "clear_tuning",
+    "ParamSet",
+    "batch_layout",
+    "BatchPlan",
     "U16",
     "F32",
 ]
@@ -40,6 +46,20 @@ U16, F32 = 0, 1
 _STATUS = {0: "NRR_OK", 1: "NRR_ERR_INVALID_ARG", 2: "NRR_ERR_BUFFER_TOO_SMALL", 3: "NRR_ERR_HIP",
            4: "NRR_ERR_UNSUPPORTED"}
 _lib = None
+
+
+class TileShape(ctypes.Structure):
+    _fields_ = [("arith", ctypes.c_int32), ("rx", ctypes.c_int32), ("ry", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("pf", ctypes.c_int32), ("cz", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ParamSet(ctypes.Structure):
+    """One parameter set of the batched search (block, window, stride, fraction)."""
+    _fields_ = [("block", ctypes.c_int32), ("window", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("fraction", ctypes.c_double)]
 
 
 class NrrError(RuntimeError):
@@ -75,6 +95,15 @@ def load():
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
+        "nrr_tune_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, I32, P, P,
+                                P]),
+        "nrr_tuned_shape": (st, [ctypes.c_int, I32, I32, P]),
+        "nrr_clear_tuning": (st, []),
+        "nrr_batch_layout": (st, [ctypes.c_int, P, P, I32, P, P]),
+        "nrr_batch_plan_create": (st, [P, P, ctypes.c_int, P, P, I32, P, P, P, P, P, SZ, I32, P,
+                                       P]),
+        "nrr_batch_plan_run": (st, [P, P]),
+        "nrr_batch_plan_destroy": (st, [P]),
         "nrr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "nrr_last_error": (ctypes.c_char_p, []),
         "nrr_version": (I32, []),
@@ -224,3 +253,121 @@ def block_match(ref, flt, centers, block: int, window: int, workspace=None, out=
                                ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
     return disp, ncc, conf
+
+
+# ------------------------------------------------------------------ tuning
+
+def tune_match(ref, flt, centers, block: int, window: int, workspace=None, reps: int = 3):
+    """Time every compiled search shape for (dtype, block, window) on these
+    inputs and keep the fastest for later searches in this process.
+    Returns (shape dict, mean microseconds).  Synchronises the stream."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    n = centers.shape[0]
+    disp = torch.empty((max(n, 1), 3), dtype=torch.int32, device=ref.device)
+    ncc = torch.empty(max(n, 1), dtype=torch.float32, device=ref.device)
+    conf = torch.empty(max(n, 1), dtype=torch.float32, device=ref.device)
+    ws = workspace if workspace is not None else window_stats(flt, block)
+    best = TileShape()
+    us = ctypes.c_double()
+    _check(lib.nrr_tune_match(ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()),
+                              dt, _dims3(dims), ctypes.c_void_p(centers.data_ptr()), n, block,
+                              window, ctypes.c_void_p(disp.data_ptr()),
+                              ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(reps),
+                              ctypes.byref(best), ctypes.byref(us), _stream(ref)))
+    return best.as_dict(), us.value
+
+
+def tuned_shape(dtype: int, block: int, window: int):
+    """The tuned shape for (dtype, block, window) as a dict, or None."""
+    out = TileShape()
+    st = load().nrr_tuned_shape(dtype, block, window, ctypes.byref(out))
+    return out.as_dict() if st == 0 else None
+
+
+def clear_tuning():
+    _check(load().nrr_clear_tuning())
+
+
+# ---------------------------------------------------------- batched search
+
+def _param_array(sets):
+    arr = (ParamSet * max(len(sets), 1))()
+    for i, q in enumerate(sets):
+        if isinstance(q, ParamSet):
+            arr[i] = q
+        else:
+            b, w, stride, frac = q
+            arr[i] = ParamSet(int(b), int(w), int(stride), float(frac))
+    return arr
+
+
+def batch_layout(dtype: int, dims, sets):
+    """(row offsets per set [nsets+1], workspace bytes) of a batched search."""
+    arr = _param_array(sets)
+    offs = (ctypes.c_int64 * (len(sets) + 1))()
+    nb = ctypes.c_size_t()
+    _check(load().nrr_batch_layout(dtype, _dims3(dims), arr, len(sets), offs, ctypes.byref(nb)))
+    return list(offs), nb.value
+
+
+class BatchPlan:
+    """A batched parametric search over one volume pair.
+
+    ``sets`` are (block, window, stride, fraction) tuples.  ``run()`` enqueues
+    one batch on the current stream (a HIP graph replay with ``use_graph``);
+    ``results()`` splits the outputs into per-set (centers, disp, ncc, conf)
+    views.  Inputs must stay alive and unchanged in shape while the plan
+    lives (the plan reads them on every run)."""
+
+    def __init__(self, ref, flt, sets, use_graph: bool = True):
+        torch = _torch()
+        lib = load()
+        dt, dims = _vol_info(ref)
+        dt2, dims2 = _vol_info(flt)
+        if dt != dt2 or dims != dims2 or ref.device != flt.device:
+            raise NrrError(1, "ref and flt must share dtype, shape and device")
+        self.ref, self.flt, self.sets = ref, flt, list(sets)
+        self.offsets, nbytes = batch_layout(dt, dims, self.sets)
+        rows = max(self.offsets[-1], 1)
+        dev = ref.device
+        self.centers = torch.empty((rows, 3), dtype=torch.int32, device=dev)
+        self.disp = torch.empty((rows, 3), dtype=torch.int32, device=dev)
+        self.ncc = torch.empty(rows, dtype=torch.float32, device=dev)
+        self.conf = torch.empty(rows, dtype=torch.float32, device=dev)
+        self.workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        arr = _param_array(self.sets)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(dev)
+        _check(lib.nrr_batch_plan_create(
+            ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
+            arr, len(self.sets), ctypes.c_void_p(self.centers.data_ptr()),
+            ctypes.c_void_p(self.disp.data_ptr()), ctypes.c_void_p(self.ncc.data_ptr()),
+            ctypes.c_void_p(self.conf.data_ptr()), ctypes.c_void_p(self.workspace.data_ptr()),
+            self.workspace.numel(), 1 if use_graph else 0, _stream(ref), ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        if self._h is None:
+            raise NrrError(1, "plan closed")
+        _check(load().nrr_batch_plan_run(self._h, _stream(self.ref)))
+
+    def results(self):
+        out = []
+        for i in range(len(self.sets)):
+            a, b = self.offsets[i], self.offsets[i + 1]
+            out.append((self.centers[a:b], self.disp[a:b], self.ncc[a:b], self.conf[a:b]))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().nrr_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

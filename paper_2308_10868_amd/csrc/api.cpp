@@ -2,10 +2,14 @@
 // workspace sizing, status codes and kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
+#include <numeric>
+#include <vector>
 
 #include "nrr.h"
 #include "nrr_internal.h"
@@ -190,10 +194,10 @@ nrr_status check_match(const void *ref, const void *flt, nrr_dtype dtype, const 
     return NRR_OK;
 }
 
-nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const int32_t dims[3],
-                     const int32_t *centers, int64_t n, int32_t block, int32_t window,
-                     int32_t *disp, float *ncc, float *conf, const void *workspace,
-                     const nrr::StatsLayout &L, hipStream_t st) {
+nrr::MatchArgs match_args(const void *ref, const void *flt, const int32_t dims[3],
+                          const int32_t *centers, int64_t n, int32_t block, int32_t window,
+                          int32_t *disp, float *ncc, float *conf, const void *workspace,
+                          const nrr::StatsLayout &L) {
     nrr::MatchArgs a;
     a.ref = ref;
     a.flt = flt;
@@ -213,7 +217,81 @@ nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const in
     a.disp = disp;
     a.ncc = ncc;
     a.conf = conf;
+    return a;
+}
+
+nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                     const int32_t *centers, int64_t n, int32_t block, int32_t window,
+                     int32_t *disp, float *ncc, float *conf, const void *workspace,
+                     const nrr::StatsLayout &L, hipStream_t st) {
+    const nrr::MatchArgs a =
+        match_args(ref, flt, dims, centers, n, block, window, disp, ncc, conf, workspace, L);
     return hip_status(nrr::launch_match(dtype, a, st), "block match launch");
+}
+
+// Sizes, plans and workspace regions of a batched search.
+struct BatchLayout {
+    std::vector<int64_t> ncand, k, off;  // per set (off: nsets + 1 rows offsets)
+    std::vector<int32_t> grid;           // per set, 3 values
+    std::vector<int32_t> variant, cz;
+    std::vector<double> cost;            // per set: K times the per-block cost
+    std::vector<int32_t> bvals;          // distinct block sizes
+    std::vector<size_t> stats_off;       // per distinct block size
+    size_t sel_off = 0, sets_off = 0, total = 0, lds = 0;
+    int64_t nitems = 0;
+};
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+nrr_status batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
+                        int32_t nsets, BatchLayout *L) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    if (nsets < 0) return fail(NRR_ERR_INVALID_ARG, "nsets must be >= 0 (got %d)", nsets);
+    if (nsets > 0 && !sets) return fail(NRR_ERR_INVALID_ARG, "sets is NULL");
+    L->off.assign(1, 0);
+    for (int i = 0; i < nsets; ++i) {
+        const nrr_param_set &q = sets[i];
+        int32_t g[3];
+        if ((s = check_grid(dims, q.block, q.stride, g)) != NRR_OK) return s;
+        if (!(q.fraction > 0.0 && q.fraction <= 1.0))
+            return fail(NRR_ERR_INVALID_ARG, "set %d: fraction must be in (0, 1]", i);
+        if (q.window < 0) return fail(NRR_ERR_INVALID_ARG, "set %d: window must be >= 0", i);
+        if (q.window > 64) return fail(NRR_ERR_UNSUPPORTED, "set %d: window above 64", i);
+        const int64_t nc = (int64_t)g[0] * g[1] * g[2];
+        if (nc > nrr::kBatchCand)
+            return fail(NRR_ERR_UNSUPPORTED, "set %d: %lld candidate blocks (batched limit %d)", i,
+                        (long long)nc, nrr::kBatchCand);
+        int32_t var = 0, cz = 0;
+        size_t lds = 0;
+        double per = 0.0;
+        if (!nrr::plan_batch_set(dtype, q.block, q.window, &var, &cz, &lds, &per))
+            return fail(NRR_ERR_UNSUPPORTED, "set %d: no batched shape for block %d window %d", i,
+                        q.block, q.window);
+        const int64_t k = count_rule(nc, q.fraction);
+        L->ncand.push_back(nc);
+        L->k.push_back(k);
+        L->off.push_back(L->off.back() + k);
+        L->grid.insert(L->grid.end(), g, g + 3);
+        L->variant.push_back(var);
+        L->cz.push_back(cz);
+        L->cost.push_back(per * (double)k);
+        L->lds = std::max(L->lds, lds);
+        L->nitems += k;
+        if (std::find(L->bvals.begin(), L->bvals.end(), q.block) == L->bvals.end())
+            L->bvals.push_back(q.block);
+    }
+    size_t at = 0;
+    for (int32_t b : L->bvals) {
+        L->stats_off.push_back(at);
+        at += align256(nrr::stats_layout(dtype, dims, b).total);
+    }
+    L->sel_off = at;
+    at += align256(sizeof(nrr::BatchSelectSet) * (size_t)std::max(nsets, 1));
+    L->sets_off = at;
+    at += align256(sizeof(nrr::BatchSet) * (size_t)std::max(nsets, 1));
+    L->total = at;
+    return NRR_OK;
 }
 
 }  // namespace
@@ -263,6 +341,238 @@ nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
     if (e != hipSuccess) return hip_status(e, "window statistics launch");
     return run_match(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf, workspace,
                      L, st);
+}
+
+// ------------------------------------------------------------------ tuning
+
+nrr_status nrr_tune_match(const void *ref, const void *flt, nrr_dtype dtype,
+                          const int32_t dims[3], const int32_t *centers, int64_t n, int32_t block,
+                          int32_t window, int32_t *disp, float *ncc, float *conf,
+                          const void *workspace, size_t workspace_bytes, int32_t reps,
+                          nrr_tile_shape *best, double *best_us, void *stream) {
+    if (reps < 1) return fail(NRR_ERR_INVALID_ARG, "reps must be >= 1 (got %d)", reps);
+    nrr::StatsLayout L;
+    nrr_status s = check_match(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf,
+                               workspace, workspace_bytes, &L);
+    if (s != NRR_OK) return s;
+    if (n == 0) return fail(NRR_ERR_INVALID_ARG, "n must be > 0 to time the search");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const nrr::MatchArgs a =
+        match_args(ref, flt, dims, centers, n, block, window, disp, ncc, conf, workspace, L);
+    nrr::TileShape shapes[64];
+    const int ns = nrr::match_shapes(dtype, block, window, shapes, 64);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_status(e, "tuner event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_status(e, "tuner event");
+    }
+    double bt = std::numeric_limits<double>::infinity();
+    int bi = -1;
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        if ((e = nrr::launch_match(dtype, a, st, &shapes[i])) != hipSuccess) break;  // warm-up
+        if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = nrr::launch_match(dtype, a, st, &shapes[i]);
+        if (e != hipSuccess) break;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        const double us = 1000.0 * ms / reps;
+        if (us < bt) {
+            bt = us;
+            bi = i;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_status(e, "tuner trial");
+    if (bi < 0) return fail(NRR_ERR_UNSUPPORTED, "no compiled shape for block %d window %d", block,
+                            window);
+    // leave the outputs as the chosen shape computes them
+    nrr::set_tuned_shape(dtype, block, window, shapes[bi]);
+    if ((e = nrr::launch_match(dtype, a, st, &shapes[bi])) != hipSuccess)
+        return hip_status(e, "block match launch");
+    if (best) {
+        const nrr::TileShape &t = shapes[bi];
+        *best = nrr_tile_shape{t.arith, t.rx, t.ry, t.nt, t.pf, t.cz};
+    }
+    if (best_us) *best_us = bt;
+    return ok();
+}
+
+nrr_status nrr_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, nrr_tile_shape *out) {
+    nrr::TileShape t;
+    if (!out) return fail(NRR_ERR_INVALID_ARG, "out is NULL");
+    if (!nrr::tuned_shape(dtype, block, window, &t))
+        return fail(NRR_ERR_UNSUPPORTED, "no tuned shape for block %d window %d", block, window);
+    *out = nrr_tile_shape{t.arith, t.rx, t.ry, t.nt, t.pf, t.cz};
+    return ok();
+}
+
+nrr_status nrr_clear_tuning(void) {
+    nrr::clear_tuned_shapes();
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- batched search
+
+struct nrr_batch_plan {
+    const void *ref = nullptr, *flt = nullptr;
+    nrr_dtype dtype = NRR_F32;
+    int32_t dims[3] = {0, 0, 0};
+    BatchLayout L;
+    char *ws = nullptr;
+    int32_t nsets = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// The launches of one batch on `st`: window statistics per block size, the
+// batched selection, the persistent search.
+hipError_t batch_enqueue(const nrr_batch_plan &P, hipStream_t st) {
+    for (size_t i = 0; i < P.L.bvals.size(); ++i) {
+        hipError_t e = nrr::launch_stats(P.flt, P.dtype, P.dims, P.L.bvals[i],
+                                         P.ws + P.L.stats_off[i], st);
+        if (e != hipSuccess) return e;
+    }
+    if (P.nsets == 0) return hipSuccess;
+    hipError_t e = nrr::launch_select_batch(
+        P.ref, P.dtype, P.dims, reinterpret_cast<const nrr::BatchSelectSet *>(P.ws + P.L.sel_off),
+        P.nsets, st);
+    if (e != hipSuccess) return e;
+    return nrr::launch_match_batch(P.dtype,
+                                   reinterpret_cast<const nrr::BatchSet *>(P.ws + P.L.sets_off),
+                                   P.nsets, P.L.nitems, P.L.lds, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+nrr_status nrr_batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
+                            int32_t nsets, int64_t *offsets, size_t *workspace_bytes) {
+    BatchLayout L;
+    nrr_status s = batch_layout(dtype, dims, sets, nsets, &L);
+    if (s != NRR_OK) return s;
+    if (offsets) std::copy(L.off.begin(), L.off.end(), offsets);
+    if (workspace_bytes) *workspace_bytes = L.total;
+    return ok();
+}
+
+nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dtype,
+                                 const int32_t dims[3], const nrr_param_set *sets, int32_t nsets,
+                                 int32_t *centers, int32_t *disp, float *ncc, float *conf,
+                                 void *workspace, size_t workspace_bytes, int32_t use_graph,
+                                 void *stream, nrr_batch_plan **plan) {
+    if (!plan) return fail(NRR_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    nrr_batch_plan *P = new nrr_batch_plan;
+    nrr_status s = batch_layout(dtype, dims, sets, nsets, &P->L);
+    if (s != NRR_OK) {
+        delete P;
+        return s;
+    }
+    const int64_t rows = P->L.off.back();
+    if (!ref || !flt || !workspace || (rows > 0 && (!centers || !disp || !ncc || !conf))) {
+        delete P;
+        return fail(NRR_ERR_INVALID_ARG, "volume, output and workspace pointers must be non-NULL");
+    }
+    if (workspace_bytes < P->L.total) {
+        const size_t need = P->L.total;
+        delete P;
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes, need);
+    }
+    P->ref = ref;
+    P->flt = flt;
+    P->dtype = dtype;
+    std::copy(dims, dims + 3, P->dims);
+    P->ws = static_cast<char *>(workspace);
+    P->nsets = nsets;
+    // set tables: selection in the caller's order, search by falling cost
+    std::vector<nrr::BatchSelectSet> sel(nsets);
+    std::vector<nrr::BatchSet> bs(nsets);
+    std::vector<int> order(nsets);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return P->L.cost[x] > P->L.cost[y]; });
+    int64_t item = 0;
+    for (int j = 0; j < nsets; ++j) {
+        const int i = order[j];
+        const nrr_param_set &q = sets[i];
+        const int64_t off = P->L.off[i];
+        nrr::BatchSelectSet &t = sel[i];
+        t.b = q.block;
+        t.stride = q.stride;
+        t.gx = P->L.grid[3 * i];
+        t.gy = P->L.grid[3 * i + 1];
+        t.gz = P->L.grid[3 * i + 2];
+        t.pad = 0;
+        t.ncand = P->L.ncand[i];
+        t.k = P->L.k[i];
+        t.centers = centers ? centers + 3 * off : nullptr;
+        const size_t bi =
+            std::find(P->L.bvals.begin(), P->L.bvals.end(), q.block) - P->L.bvals.begin();
+        const nrr::StatsLayout SL = nrr::stats_layout(dtype, dims, q.block);
+        const char *stats = P->ws + P->L.stats_off[bi];
+        nrr::BatchSet &b = bs[j];
+        b.a = match_args(ref, flt, dims, t.centers, t.k, q.block, q.window,
+                         disp ? disp + 3 * off : nullptr, ncc ? ncc + off : nullptr,
+                         conf ? conf + off : nullptr, stats, SL);
+        b.cz = P->L.cz[i];
+        b.variant = P->L.variant[i];
+        b.first_item = item;
+        item += t.k;
+    }
+    hipError_t e = hipSuccess;
+    if (nsets > 0) {
+        e = hipMemcpy(P->ws + P->L.sel_off, sel.data(), sizeof(nrr::BatchSelectSet) * nsets,
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(P->ws + P->L.sets_off, bs.data(), sizeof(nrr::BatchSet) * nsets,
+                          hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && use_graph) {
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t ee = batch_enqueue(*P, cs);
+                e = hipStreamEndCapture(cs, &P->graph);
+                if (ee != hipSuccess) e = ee;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+            hipStreamDestroy(cs);
+        }
+    }
+    (void)stream;
+    if (e != hipSuccess) {
+        nrr_batch_plan_destroy(P);
+        return hip_status(e, "batch plan");
+    }
+    *plan = P;
+    return ok();
+}
+
+nrr_status nrr_batch_plan_run(nrr_batch_plan *plan, void *stream) {
+    if (!plan) return fail(NRR_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (plan->exec) return hip_status(hipGraphLaunch(plan->exec, st), "batch graph launch");
+    return hip_status(batch_enqueue(*plan, st), "batch launch");
+}
+
+nrr_status nrr_batch_plan_destroy(nrr_batch_plan *plan) {
+    if (!plan) return ok();
+    if (plan->exec) hipGraphExecDestroy(plan->exec);
+    if (plan->graph) hipGraphDestroy(plan->graph);
+    delete plan;
+    return ok();
 }
 
 }  // extern "C"

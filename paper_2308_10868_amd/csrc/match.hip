@@ -38,7 +38,9 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "nrr_internal.h"
 
@@ -412,8 +414,21 @@ __device__ __attribute__((always_inline)) inline void rank_tile(
         }
 }
 
+// Workgroup scratch of the reductions (any NT <= 1024).
+struct Small {
+    double key[16];
+    int idx[16];
+    long long red[16 * 5];
+    double redd[16 * 3];
+};
+
+// Search of one block `blk` (its window staged in `lds`); the body shared by
+// the per-block kernel and the batched kernel.  Every thread of the NT-wide
+// workgroup calls it; it ends with all LDS reads done by the thread itself,
+// so a caller that reuses LDS for another block synchronises first.
 template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
-__global__ __launch_bounds__(NT) void k_match(Params p) {
+__device__ __attribute__((always_inline)) inline void match_one(const Params &p, int64_t blk,
+                                                                unsigned char *lds, Small &sm) {
     constexpr bool U16 = sizeof(Vox) == 2;
     static_assert(ARITH == FMA || U16, "DOT2 needs 12-bit data");
     constexpr int H = (B - 1) / 2, N = B * B * B, BP = (B + 3) & ~3;
@@ -421,15 +436,14 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
     constexpr int TPL = ARITH == DOT2 ? P : B;  // block planes (pairs) in the T table
     constexpr int TP_WORDS = TPL * B * BP;
     using KeyT = typename std::conditional<U16, float, double>::type;
-    extern __shared__ __align__(16) unsigned char lds[];
     uint32_t *tp = reinterpret_cast<uint32_t *>(lds);                  // [TPL][B][BP]
     uint32_t *win = reinterpret_cast<uint32_t *>(lds + TP_WORDS * 4);  // [cz+B-1][PY][PX]
-    __shared__ KeyT s_key[NT / 64];
-    __shared__ int s_idx[NT / 64];
-    __shared__ long long s_red[(NT / 64) * 5];
-    __shared__ double s_redd[(NT / 64) * 3];
+    KeyT *s_key = reinterpret_cast<KeyT *>(sm.key);
+    int *s_idx = sm.idx;
+    long long *s_red = sm.red;
+    double *s_redd = sm.redd;
+    static_assert(NT <= 1024, "reduction scratch is sized for 16 wavefronts");
 
-    const int64_t blk = p.first + xcd_block(blockIdx.x, gridDim.x);
     const Geom g = make_geom(p, blk, H);
     const int tid = threadIdx.x;
     if (!g.inside) {
@@ -725,6 +739,69 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
 }
 
 
+template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
+__global__ __launch_bounds__(NT) void k_match(Params p) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ Small sm;
+    match_one<Vox, ARITH, B, RX, RY, NT, PF>(p, p.first + xcd_block(blockIdx.x, gridDim.x), lds,
+                                             sm);
+}
+
+
+// ------------------------------------------------------------ batched search
+//
+// Many parameter sets (block size, window, selection) over one volume pair in
+// one persistent launch: workgroups stride a list of work items (the blocks
+// of every set, the most expensive sets first) and switch to the compiled
+// shape the set was planned with.  The shapes all run 256 threads.
+#define BATCH_F32(X) X(0, 5, 4, 4, 0) X(1, 7, 4, 4, 0) X(2, 9, 4, 4, 0) X(3, 5, 3, 3, 0) \
+    X(4, 7, 3, 3, 0) X(5, 9, 3, 3, 0)
+#define BATCH_U16(X) X(0, 5, 4, 4, 0) X(1, 7, 3, 7, 1) X(2, 7, 4, 4, 0) X(3, 9, 4, 4, 0) \
+    X(4, 9, 5, 5, 0) X(5, 5, 3, 3, 0)
+
+template <typename Vox>
+__global__ __launch_bounds__(256) void k_match_batch(const BatchSet *__restrict__ sets, int nsets,
+                                                     int64_t nitems) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ Small sm;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int s = 0;
+        while (s + 1 < nsets && sets[s + 1].first_item <= it) ++s;
+        const BatchSet &S = sets[s];
+        Params p;
+        p.ref = S.a.ref;
+        p.flt = S.a.flt;
+        p.nx = S.a.nx;
+        p.ny = S.a.ny;
+        p.nz = S.a.nz;
+        p.centers = S.a.centers;
+        p.n = S.a.n;
+        p.first = 0;
+        p.w = S.a.window;
+        p.cz = S.cz;
+        p.stats = S.a.stats;
+        p.pv = S.a.pairs;
+        p.ox = S.a.ox;
+        p.oy = S.a.oy;
+        p.disp = S.a.disp;
+        p.ncc = S.a.ncc;
+        p.conf = S.a.conf;
+        const int64_t blk = it - S.first_item;
+        if constexpr (sizeof(Vox) == 4) {
+#define CASE_F32(ID, B, RX, RY, PF) \
+    case ID: match_one<float, FMA, B, RX, RY, 256, PF>(p, blk, lds, sm); break;
+            switch (S.variant) { BATCH_F32(CASE_F32) }
+#undef CASE_F32
+        } else {
+#define CASE_U16(ID, B, RX, RY, PF) \
+    case ID: match_one<uint16_t, DOT2, B, RX, RY, 256, PF>(p, blk, lds, sm); break;
+            switch (S.variant) { BATCH_U16(CASE_U16) }
+#undef CASE_U16
+        }
+        __syncthreads();  // the next item restages LDS
+    }
+}
+
 // ------------------------------------------------------------ dispatch
 
 typedef void (*kernel_t)(Params);
@@ -823,31 +900,46 @@ int arith_preference() {
     return -1;
 }
 
-// Tuning overrides (for measurement sweeps and the tile tuner): NRR_TILE=
-// "rx,ry,nt[,pf]" restricts the variant, NRR_CZ=n caps the z-chunk.  Unknown or
-// infeasible values are ignored.
-void tile_override(int *rx, int *ry, int *nt, int *pf, int *cz) {
-    *rx = *ry = *nt = *cz = 0;
-    *pf = -1;
-    if (const char *e = getenv("NRR_TILE")) sscanf(e, "%d,%d,%d,%d", rx, ry, nt, pf);
-    if (const char *e = getenv("NRR_CZ")) *cz = atoi(e);
+// Measurement overrides: NRR_TILE="rx,ry,nt[,pf]" restricts the shape and
+// NRR_CZ=n caps the z-chunk (unknown or infeasible values are ignored).
+bool shape_from_env(TileShape *sh) {
+    *sh = TileShape{-1, 0, 0, 0, -1, 0};
+    if (const char *e = getenv("NRR_TILE")) sscanf(e, "%d,%d,%d,%d", &sh->rx, &sh->ry, &sh->nt, &sh->pf);
+    if (const char *e = getenv("NRR_CZ")) sh->cz = atoi(e);
+    return sh->rx > 0 || sh->cz > 0;
 }
 
-bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, Plan *best) {
-    int orx, ory, ont, opf, ocz;
-    tile_override(&orx, &ory, &ont, &opf, &ocz);
-    for (int pass = 0; pass < 2; ++pass) {  // pass 0 honours the overrides
+// Shapes chosen by the tuner, per (dtype, block, window), for the process.
+struct TunedEntry {
+    nrr_dtype dtype;
+    int b, w;
+    TileShape sh;
+};
+std::mutex g_tuned_mu;
+std::vector<TunedEntry> g_tuned;
+
+bool shape_matches(const Variant &v, const TileShape &sh) {
+    if (sh.arith >= 0 && v.arith != sh.arith) return false;
+    if (sh.rx > 0 && (v.rx != sh.rx || v.ry != sh.ry || v.nt != sh.nt)) return false;
+    if (sh.pf >= 0 && v.pf != sh.pf) return false;
+    return true;
+}
+
+// Best plan by the cost model among compiled shapes of (dtype, b); `force`
+// (when given and feasible) restricts the shape and caps the z-chunk.
+bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, const TileShape *force,
+                 Plan *best) {
+    for (int pass = force ? 0 : 1; pass < 2; ++pass) {
         bool found = false;
         double bc = 0.0;
         for (const Variant &v : kVariants) {
             if (v.dtype != dtype || v.b != b) continue;
             if (arith >= 0 && v.arith != arith) continue;
-            if (pass == 0 && orx > 0 && (v.rx != orx || v.ry != ory || v.nt != ont)) continue;
-            if (pass == 0 && opf >= 0 && v.pf != opf) continue;
+            if (pass == 0 && !shape_matches(v, *force)) continue;
             Plan pl;
             if (!plan_variant(v, w, limit, limit / 2, &pl)) continue;
-            if (pass == 0 && ocz > 0 && ocz < pl.cz) {
-                const int d = 2 * w + 1, nch = (d + ocz - 1) / ocz;
+            if (pass == 0 && force->cz > 0 && force->cz < pl.cz) {
+                const int d = 2 * w + 1, nch = (d + force->cz - 1) / force->cz;
                 pl.cz = (d + nch - 1) / nch;
                 pl.lds = t_table_bytes(v) + (size_t)(pl.cz + v.b - 1) * window_plane_bytes(v, w);
             }
@@ -863,12 +955,16 @@ bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, Plan *b
     return false;
 }
 
-// NRR_ARITH=dot2|fma restricts 12-bit volumes to one arithmetic form (float
-// volumes only have the FMA form); otherwise the cost model decides.
-bool choose(nrr_dtype dtype, int b, int w, size_t limit, Plan *best) {
+// Shape priority: an explicit one (the tuner's trials), the environment
+// overrides, the tuned table, then the cost model.  NRR_ARITH=dot2|fma
+// restricts 12-bit volumes to one arithmetic form.
+bool choose(nrr_dtype dtype, int b, int w, size_t limit, const TileShape *force, Plan *best) {
+    TileShape sh;
+    if (!force && shape_from_env(&sh)) force = &sh;
+    if (!force && tuned_shape(dtype, b, w, &sh)) force = &sh;
     const int pref = arith_preference();
-    if (pref >= 0 && choose_with(dtype, b, w, limit, pref, best)) return true;
-    return choose_with(dtype, b, w, limit, -1, best);
+    if (pref >= 0 && choose_with(dtype, b, w, limit, pref, force, best)) return true;
+    return choose_with(dtype, b, w, limit, -1, force, best);
 }
 
 }  // namespace
@@ -893,14 +989,135 @@ const char *match_unsupported_reason(nrr_dtype dtype, int32_t block, int32_t win
     if (block > MAX_B) return "block edge above 15 is not built";
     if (window > 64) return "window above 64 is not supported";
     Plan pl;
-    if (!choose(dtype, block, window, device_lds_limit(), &pl))
+    if (!choose(dtype, block, window, device_lds_limit(), nullptr, &pl))
         return "one window plane does not fit in LDS for this block size";
     return nullptr;
 }
 
-hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream) {
+
+namespace {
+#define ROW_F32(ID, B, RX, RY, PF) {NRR_F32, FMA, B, RX, RY, 256, PF, nullptr},
+#define ROW_U16(ID, B, RX, RY, PF) {NRR_U16, DOT2, B, RX, RY, 256, PF, nullptr},
+const Variant kBatchF32[] = {BATCH_F32(ROW_F32)};
+const Variant kBatchU16[] = {BATCH_U16(ROW_U16)};
+#undef ROW_F32
+#undef ROW_U16
+}  // namespace
+
+bool plan_batch_set(nrr_dtype dtype, int32_t block, int32_t window, int32_t *variant,
+                    int32_t *cz, size_t *lds, double *cost_per_block) {
+    const Variant *tab = dtype == NRR_F32 ? kBatchF32 : kBatchU16;
+    const int nv = dtype == NRR_F32 ? (int)(sizeof(kBatchF32) / sizeof(Variant))
+                                    : (int)(sizeof(kBatchU16) / sizeof(Variant));
+    const size_t limit = device_lds_limit();
+    // a tuned shape for this (dtype, block, window) wins when it is compiled here
+    TileShape ts;
+    const bool tuned = tuned_shape(dtype, block, window, &ts);
+    bool found = false;
+    double best = 0.0;
+    for (int pass = 0; pass < 2 && !found; ++pass)
+        for (int i = 0; i < nv; ++i) {
+            const Variant &v = tab[i];
+            if (v.b != block) continue;
+            if (pass == 0 && (!tuned || !shape_matches(v, ts))) continue;
+            Plan pl;
+            if (!plan_variant(v, window, limit, limit / 2, &pl)) continue;
+            if (pass == 0 && ts.cz > 0 && ts.cz < pl.cz) {
+                const int d = 2 * window + 1, nch = (d + ts.cz - 1) / ts.cz;
+                pl.cz = (d + nch - 1) / nch;
+                pl.lds = t_table_bytes(v) + (size_t)(pl.cz + v.b - 1) * window_plane_bytes(v, window);
+            }
+            const double c = plan_cost(pl, window);
+            if (!found || c < best) {
+                best = c;
+                *variant = i;
+                *cz = pl.cz;
+                *lds = pl.lds;
+                *cost_per_block = c;
+                found = true;
+            }
+        }
+    return found;
+}
+
+hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nsets,
+                              int64_t nitems, size_t lds, hipStream_t stream) {
+    if (nitems <= 0) return hipSuccess;
+    const void *fn = dtype == NRR_F32 ? reinterpret_cast<const void *>(k_match_batch<float>)
+                                      : reinterpret_cast<const void *>(k_match_batch<uint16_t>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = dtype == NRR_F32
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_match_batch<float>, 256, lds)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_match_batch<uint16_t>, 256,
+                                                           lds);
+    if (e != hipSuccess) return e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    const unsigned grid = (unsigned)(nitems < slots ? nitems : slots);
+    if (dtype == NRR_F32)
+        hipLaunchKernelGGL(k_match_batch<float>, dim3(grid), dim3(256), lds, stream, sets, nsets,
+                           nitems);
+    else
+        hipLaunchKernelGGL(k_match_batch<uint16_t>, dim3(grid), dim3(256), lds, stream, sets,
+                           nsets, nitems);
+    return hipGetLastError();
+}
+
+bool tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, TileShape *sh) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    for (const TunedEntry &t : g_tuned)
+        if (t.dtype == dtype && t.b == block && t.w == window) {
+            *sh = t.sh;
+            return true;
+        }
+    return false;
+}
+
+void set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, const TileShape &sh) {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    for (TunedEntry &t : g_tuned)
+        if (t.dtype == dtype && t.b == block && t.w == window) {
+            t.sh = sh;
+            return;
+        }
+    g_tuned.push_back(TunedEntry{dtype, block, window, sh});
+}
+
+void clear_tuned_shapes() {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned.clear();
+}
+
+int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out, int cap) {
+    const size_t limit = device_lds_limit();
+    const int d = 2 * window + 1;
+    int n = 0;
+    for (const Variant &v : kVariants) {
+        if (v.dtype != dtype || v.b != block) continue;
+        Plan pl;
+        if (!plan_variant(v, window, limit, limit / 2, &pl)) continue;
+        // the planned z-chunk and the next two finer splits of the window
+        int last = 0;
+        for (int nch = (d + pl.cz - 1) / pl.cz; nch <= (d + pl.cz - 1) / pl.cz + 2; ++nch) {
+            const int cz = (d + nch - 1) / nch;
+            if (cz == last || cz < 1) continue;
+            last = cz;
+            if (n < cap) out[n] = TileShape{v.arith, v.rx, v.ry, v.nt, v.pf, cz};
+            ++n;
+        }
+    }
+    return n < cap ? n : cap;
+}
+
+hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
+                        const TileShape *shape) {
     Plan pl;
-    if (!choose(dtype, a.block, a.window, device_lds_limit(), &pl)) return hipErrorInvalidValue;
+    if (!choose(dtype, a.block, a.window, device_lds_limit(), shape, &pl))
+        return hipErrorInvalidValue;
     const Variant *v = pl.v;
     if (hipFuncSetAttribute(reinterpret_cast<const void *>(v->fn),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds) != hipSuccess)

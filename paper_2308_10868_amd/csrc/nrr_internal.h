@@ -26,6 +26,18 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
                          int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
                          void *workspace, hipStream_t stream);
 
+// Batched selection (one workgroup per parameter set) for candidate grids of
+// at most kBatchCand blocks; `centers` points at the set's K output rows.
+constexpr int kBatchCand = 4096;
+struct BatchSelectSet {
+    int32_t b, stride, gx, gy, gz;
+    int32_t pad;
+    int64_t ncand, k;
+    int32_t *centers;
+};
+hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                               const BatchSelectSet *sets, int nsets, hipStream_t stream);
+
 // ---------------------------------------------------------- window stats
 // Per-voxel statistics of the displaced block whose origin (lowest corner)
 // is that voxel, over the origin grid O = dims - block + 1, one record per
@@ -74,7 +86,38 @@ struct MatchArgs {
 // Returns 0 when supported, else a static reason string.
 const char *match_unsupported_reason(nrr_dtype dtype, int32_t block, int32_t window);
 
-hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream);
+// ------------------------------------------------------- batched matching
+// One parameter set of a batched search: its arguments (centres and outputs
+// already offset to the set's rows), z-chunk, compiled tile shape and first
+// work item (items = the set's blocks, sets ordered by falling cost).
+struct BatchSet {
+    MatchArgs a;
+    int32_t cz, variant;
+    int64_t first_item;
+};
+// Tile shape, z-chunk and LDS bytes of one set in the batched kernel; false
+// when no compiled batched shape serves (dtype, block, window).
+bool plan_batch_set(nrr_dtype dtype, int32_t block, int32_t window, int32_t *variant,
+                    int32_t *cz, size_t *lds, double *cost_per_block);
+// Persistent launch over all sets' blocks: `grid` workgroups stride the work
+// items; `lds` is the largest set's need.
+hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nsets,
+                              int64_t nitems, size_t lds, hipStream_t stream);
+
+// A compiled search shape: arithmetic (0 dot2, 1 FMA, -1 any), tile rx x ry
+// (0: any), threads, record prefetch (-1 any) and z-chunk cap (0: planned).
+struct TileShape {
+    int32_t arith, rx, ry, nt, pf, cz;
+};
+// `shape` (optional) forces the shape; else env overrides, tuned table, cost model.
+hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
+                        const TileShape *shape = nullptr);
+// The shapes worth timing for (dtype, block, window); returns how many (<= cap).
+int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out, int cap);
+// Process-wide table of tuned shapes used by every later launch.
+bool tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, TileShape *sh);
+void set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, const TileShape &sh);
+void clear_tuned_shapes();
 
 // LDS bytes per workgroup available on the current device (cached).
 size_t device_lds_limit();

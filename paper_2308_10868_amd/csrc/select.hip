@@ -55,14 +55,11 @@ __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restri
     if (lane == 0) keys[g] = (uint64_t)b * b * b * q - s * s;  // >= 0 by Cauchy-Schwarz
 }
 
-__global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
-                                                        int ny, int b, int stride, int gx, int gy,
-                                                        int64_t n, uint64_t *__restrict__ keys) {
+// FP64 two-pass variance of the block at (x0, y0, z0), summed in z, y, x
+// order without contraction; returned as its (monotone) bit pattern.
+__device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int b,
+                                   int64_t x0, int64_t y0, int64_t z0) {
 #pragma clang fp contract(off)
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
-    int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
     double nb = (double)b * b * b;
     double sum = 0.0;
     for (int z = 0; z < b; ++z)
@@ -81,7 +78,32 @@ __global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict_
             }
         }
     double var = ss / nb;
-    keys[g] = __double_as_longlong(var);  // var >= +0: bit pattern is monotone
+    return (uint64_t)__double_as_longlong(var);  // var >= +0: bit pattern is monotone
+}
+
+// Exact N*sum(x^2) - (sum x)^2 of the block at (x0, y0, z0), one thread.
+__device__ inline uint64_t key_u16(const uint16_t *__restrict__ vol, int nx, int ny, int b,
+                                   int64_t x0, int64_t y0, int64_t z0) {
+    uint64_t s = 0, q = 0;
+    for (int z = 0; z < b; ++z)
+        for (int y = 0; y < b; ++y) {
+            const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+            for (int x = 0; x < b; ++x) {
+                const uint64_t v = row[x];
+                s += v;
+                q += v * v;
+            }
+        }
+    return (uint64_t)b * b * b * q - s * s;
+}
+
+__global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
+                                                        int ny, int b, int stride, int gx, int gy,
+                                                        int64_t n, uint64_t *__restrict__ keys) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+    keys[g] = key_f32(vol, nx, ny, b, ix * stride, iy * stride, iz * stride);
 }
 
 // Count `d` (< 256) into the LDS histogram.  A wavefront whose counted lanes
@@ -308,7 +330,88 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ ke
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Batched selection for small candidate grids: one workgroup per parameter
+// set keys its candidates (one thread per block), sorts (key descending,
+// grid index ascending) with a bitonic network in LDS, keeps the first K and
+// writes their centres in ascending grid index.  Same keys and tie rule as
+// the radix-select path, so the same blocks come out.
+__global__ __launch_bounds__(256) void k_select_batch(const void *__restrict__ vol, int is_u16,
+                                                      int nx, int ny,
+                                                      const BatchSelectSet *__restrict__ sets) {
+    __shared__ uint64_t key[kBatchCand];
+    __shared__ uint16_t idx[kBatchCand];
+    __shared__ uint8_t sel[kBatchCand];
+    __shared__ int wsum[4];
+    const BatchSelectSet S = sets[blockIdx.x];
+    const int tid = threadIdx.x, n = (int)S.ncand;
+    int n2 = 1;
+    while (n2 < n) n2 <<= 1;
+    for (int i = tid; i < n2; i += 256) {
+        uint64_t kv = 0;  // padding sorts after every candidate (largest index)
+        if (i < n) {
+            const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
+            const int64_t x0 = (int64_t)ix * S.stride, y0 = (int64_t)iy * S.stride,
+                          z0 = (int64_t)iz * S.stride;
+            kv = is_u16 ? key_u16(static_cast<const uint16_t *>(vol), nx, ny, S.b, x0, y0, z0)
+                        : key_f32(static_cast<const float *>(vol), nx, ny, S.b, x0, y0, z0);
+        }
+        key[i] = kv;
+        idx[i] = (uint16_t)(i < n ? i : 0xffff);
+        if (i < n) sel[i] = 0;
+    }
+    __syncthreads();
+    auto before = [&](int a, int c) {  // a ranks before c
+        return key[a] > key[c] || (key[a] == key[c] && idx[a] < idx[c]);
+    };
+    for (int k = 2; k <= n2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = tid; i < n2; i += 256) {
+                const int l = i ^ j;
+                if (l > i && (((i & k) == 0) ? before(l, i) : before(i, l))) {
+                    const uint64_t tk = key[i];
+                    key[i] = key[l];
+                    key[l] = tk;
+                    const uint16_t ti = idx[i];
+                    idx[i] = idx[l];
+                    idx[l] = ti;
+                }
+            }
+            __syncthreads();
+        }
+    for (int i = tid; i < S.k; i += 256) sel[idx[i]] = 1;
+    __syncthreads();
+    // ordered compaction: each thread owns a run of consecutive candidates
+    const int per = (n + 255) / 256, lo = min(n, tid * per), hi = min(n, lo + per);
+    int cnt = 0;
+    for (int i = lo; i < hi; ++i) cnt += sel[i];
+    int incl = cnt;  // inclusive scan over the wavefront, then over wavefronts
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off);
+        if ((tid & 63) >= off) incl += o;
+    }
+    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
+    __syncthreads();
+    int pos = incl - cnt;
+    for (int w = 0; w < (tid >> 6); ++w) pos += wsum[w];
+    const int h = (S.b - 1) / 2;
+    for (int i = lo; i < hi; ++i)
+        if (sel[i]) {
+            const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
+            S.centers[3 * pos] = ix * S.stride + h;
+            S.centers[3 * pos + 1] = iy * S.stride + h;
+            S.centers[3 * pos + 2] = iz * S.stride + h;
+            ++pos;
+        }
+}
+
 }  // namespace
+
+hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                               const BatchSelectSet *sets, int nsets, hipStream_t stream) {
+    hipLaunchKernelGGL(k_select_batch, dim3((unsigned)nsets), dim3(256), 0, stream, vol,
+                       dtype == NRR_U16 ? 1 : 0, dims[0], dims[1], sets);
+    return hipGetLastError();
+}
 
 SelectLayout select_layout(int64_t n_candidates) {
     SelectLayout L;

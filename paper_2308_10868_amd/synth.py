@@ -274,3 +274,15 @@ def gen_random(seed: int, dims, dtype: str = "u16", smooth: float = 0.0) -> Volu
         b = gaussian_filter(b, smooth)
     return VolumePair(a.astype(np.float32), b.astype(np.float32), tuple(dims),
                       {"workload": "random_f32", "seed": seed})
+
+
+def gen_param_sets(n: int = 32, seed: int = 1, blocks=(5, 7, 9), windows=(5, 8, 12),
+                   fractions=(0.05, 0.1, 0.25, 0.5)):
+    """Parameter sets of the batched parametric search: (block, window,
+    stride, fraction) with block, window and fraction drawn uniformly from
+    the given choices and the grid stride equal to the block size."""
+    (r,) = _streams(seed, 1)
+    b = r.choice(np.asarray(blocks), size=n)
+    w = r.choice(np.asarray(windows), size=n)
+    f = r.choice(np.asarray(fractions, dtype=np.float64), size=n)
+    return [(int(b[i]), int(w[i]), int(b[i]), float(f[i])) for i in range(n)]

@@ -133,3 +133,41 @@ def test_product_path_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(nrr, "_lib", None)
     with pytest.raises(nrr.NrrError):
         nrr.load()
+
+
+def test_batch_layout_offsets_and_errors(lib):
+    import ctypes
+
+    import paper_2308_10868_amd as nrr
+
+    dims = (64, 64, 64)
+    sets = [(5, 5, 5, 0.05), (7, 8, 7, 0.5), (9, 12, 9, 0.25), (9, 5, 9, 0.001)]
+    offs, nbytes = nrr.batch_layout(nrr.F32, dims, sets)
+    ks = [nrr.select_count(dims, b, s, f) for b, w, s, f in sets]
+    assert offs == list(np.cumsum([0] + ks)) and nbytes > 0
+    assert ks[-1] == 0  # an empty set is allowed
+    with pytest.raises(nrr.NrrError) as e:
+        nrr.batch_layout(nrr.F32, dims, [(5, 3, 1, 0.1)])  # 60^3 candidates
+    assert e.value.status == 4
+    for bad in [(6, 3, 6, 0.1), (5, -1, 5, 0.1), (5, 3, 0, 0.1), (5, 3, 5, 0.0), (99, 3, 5, 0.5)]:
+        with pytest.raises(nrr.NrrError) as e:
+            nrr.batch_layout(nrr.F32, dims, [bad])
+        assert e.value.status == 1, bad
+    assert nrr.batch_layout(nrr.U16, dims, []) [0] == [0]
+
+
+def test_tuning_table_host_calls(lib):
+    import paper_2308_10868_amd as nrr
+
+    nrr.clear_tuning()
+    assert nrr.tuned_shape(nrr.U16, 7, 10) is None
+
+
+def test_param_sets_generator():
+    from paper_2308_10868_amd import synth
+
+    a = synth.gen_param_sets(32, seed=1)
+    assert a == synth.gen_param_sets(32, seed=1) and len(a) == 32
+    for b, w, s, f in a:
+        assert b in (5, 7, 9) and w in (5, 8, 12) and s == b and f in (0.05, 0.1, 0.25, 0.5)
+    assert len({(b, w, f) for b, w, s, f in a}) > 10
