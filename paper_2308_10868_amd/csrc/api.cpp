@@ -237,8 +237,8 @@ struct BatchLayout {
     std::vector<double> cost;            // per set: K times the per-block cost
     std::vector<int32_t> bvals;          // distinct block sizes
     std::vector<size_t> stats_off;       // per distinct block size
-    size_t sel_off = 0, sets_off = 0, total = 0, lds = 0;
-    int64_t nitems = 0;
+    size_t sel_off = 0, sets_off = 0, keys_off = 0, total = 0, lds = 0;
+    int64_t nitems = 0, max_cand = 0, sum_cand = 0;
 };
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
@@ -278,6 +278,8 @@ nrr_status batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_
         L->cost.push_back(per * (double)k);
         L->lds = std::max(L->lds, lds);
         L->nitems += k;
+        L->max_cand = std::max(L->max_cand, nc);
+        L->sum_cand += nc;
         if (std::find(L->bvals.begin(), L->bvals.end(), q.block) == L->bvals.end())
             L->bvals.push_back(q.block);
     }
@@ -290,6 +292,8 @@ nrr_status batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_
     at += align256(sizeof(nrr::BatchSelectSet) * (size_t)std::max(nsets, 1));
     L->sets_off = at;
     at += align256(sizeof(nrr::BatchSet) * (size_t)std::max(nsets, 1));
+    L->keys_off = at;
+    at += align256(sizeof(uint64_t) * (size_t)std::max<int64_t>(L->sum_cand, 1));
     L->total = at;
     return NRR_OK;
 }
@@ -444,7 +448,7 @@ hipError_t batch_enqueue(const nrr_batch_plan &P, hipStream_t st) {
     if (P.nsets == 0) return hipSuccess;
     hipError_t e = nrr::launch_select_batch(
         P.ref, P.dtype, P.dims, reinterpret_cast<const nrr::BatchSelectSet *>(P.ws + P.L.sel_off),
-        P.nsets, st);
+        P.nsets, P.L.max_cand, st);
     if (e != hipSuccess) return e;
     return nrr::launch_match_batch(P.dtype,
                                    reinterpret_cast<const nrr::BatchSet *>(P.ws + P.L.sets_off),
@@ -502,6 +506,8 @@ nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dty
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return P->L.cost[x] > P->L.cost[y]; });
     int64_t item = 0;
+    std::vector<int64_t> key_at(nsets + 1, 0);
+    for (int i = 0; i < nsets; ++i) key_at[i + 1] = key_at[i] + P->L.ncand[i];
     for (int j = 0; j < nsets; ++j) {
         const int i = order[j];
         const nrr_param_set &q = sets[i];
@@ -516,6 +522,7 @@ nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dty
         t.ncand = P->L.ncand[i];
         t.k = P->L.k[i];
         t.centers = centers ? centers + 3 * off : nullptr;
+        t.keys = reinterpret_cast<uint64_t *>(P->ws + P->L.keys_off) + key_at[i];
         const size_t bi =
             std::find(P->L.bvals.begin(), P->L.bvals.end(), q.block) - P->L.bvals.begin();
         const nrr::StatsLayout SL = nrr::stats_layout(dtype, dims, q.block);

@@ -281,6 +281,61 @@ __device__ inline void stage_rows(const uint32_t *__restrict__ src, int nx, int 
     }
 }
 
+// The same row-chunk staging for float volumes, storing F - c: a chunk that
+// would run past the end of a volume row (the window's right edge at the
+// volume border) reads its elements one by one, clamped into the row (the
+// extra values only feed masked displacements).
+template <int NT, int UNR>
+__device__ inline void stage_rows_f32(const float *__restrict__ src, int nx, int ny, int x0, int y0,
+                                      int z0, int ey, uint32_t *__restrict__ dst, int pitch,
+                                      int plane, int py, int pz, float c) {
+    using V = typename Chunk<CW>::type;
+    const int cpr = pitch / CW;
+    const int total = pz * py * cpr;
+    const int drow = NT / cpr, dxc = NT - drow * cpr;
+    int row = (int)threadIdx.x / cpr;
+    int xc = (int)threadIdx.x - row * cpr;
+    int z = row / py, y = row - z * py;
+    for (int c0 = 0; c0 < total; c0 += NT * UNR) {
+        float v[UNR][CW];
+        int off[UNR];
+        bool live[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            live[u] = c0 + u * NT + (int)threadIdx.x < total;
+            const int zz = live[u] ? z : 0, yy = min(y, ey - 1), xs = x0 + CW * xc;
+            const float *r = src + ((int64_t)(z0 + zz) * ny + (y0 + yy)) * nx;
+            if (xs + CW <= nx) {
+                const V w = *reinterpret_cast<const V *>(r + xs);
+#pragma unroll
+                for (int e = 0; e < CW; ++e) v[u][e] = __uint_as_float(w[e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < CW; ++e) v[u][e] = r[min(xs + e, nx - 1)];
+            }
+            off[u] = z * plane + y * pitch + CW * xc;
+            xc += dxc;
+            y += drow;
+            if (xc >= cpr) {
+                xc -= cpr;
+                ++y;
+            }
+            while (y >= py) {
+                y -= py;
+                ++z;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (live[u]) {
+                V w;
+#pragma unroll
+                for (int e = 0; e < CW; ++e) w[e] = __float_as_uint(v[u][e] - c);
+                *reinterpret_cast<V *>(dst + off[u]) = w;
+            }
+    }
+}
+
 // Exact int32 grouping for DOT2: a plane contributes at most B*B*2048*2048.
 template <int B>
 struct Groups {
@@ -454,8 +509,9 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
     const Vox *flt = static_cast<const Vox *>(p.flt);
     const int txn = (g.dx + RX - 1) / RX, tyn = (g.dy + RY - 1) / RY;
     const int PX = txn * RX + B - 1, PY = tyn * RY + B - 1;
-    // LDS row pitch: DOT2 rows are whole CW-word chunks
-    const int pitch = ARITH == DOT2 ? (PX + CW - 1) / CW * CW : PX;
+    // LDS row pitch: DOT2 and float windows are staged in whole CW-word chunks
+    constexpr bool ROWS = ARITH == DOT2 || !U16;
+    const int pitch = ROWS ? (PX + CW - 1) / CW * CW : PX;
     const int ex = g.dx + B - 1, ey = g.dy + B - 1;
     auto tval = [&](int o) {
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
@@ -463,13 +519,19 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
     };
 
     // ---- block statistics and the staged T table
-    // FMA: one pad dword per plane spreads LDS banks; DOT2 planes stay whole
-    // row chunks (the dz-fastest lane order spreads their banks)
-    const int plane = PY * pitch + (ARITH == DOT2 ? 0 : ZPAD);
+    // Plane stride: lanes of a wavefront take consecutive dz, so the stride
+    // spreads their reads over the LDS banks: odd (one pad dword) for the
+    // element-staged window, 4 x odd for chunk-staged windows (whole 16-byte
+    // chunks: 16 consecutive planes still hit distinct banks).
+    const int plane =
+        ROWS ? PY * pitch + (((PY * pitch / CW) & 1) ? 0 : CW) : PY * pitch + ZPAD;
     auto stage_chunk = [&](int zc0, int ezc, float c) {
         if constexpr (ARITH == DOT2)  // plain copies of the precomputed pair words
             stage_rows<NT, 8>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ey, win, pitch,
                                   plane, PY, ezc);
+        else if constexpr (!U16)
+            stage_rows_f32<NT, 4>(reinterpret_cast<const float *>(flt), p.nx, p.ny, g.wx0, g.wy0,
+                                  g.wz0 + zc0, ey, win, pitch, plane, PY, ezc, c);
         else
             stage_planes<NT, false, 4>(
                 flt, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ex, ey, ezc, win, PX, plane, PY, ezc,
@@ -850,8 +912,9 @@ size_t window_plane_bytes(const Variant &v, int w) {
     const int d = 2 * w + 1;
     const int px = (d + v.rx - 1) / v.rx * v.rx + v.b - 1;
     const int py = (d + v.ry - 1) / v.ry * v.ry + v.b - 1;
-    if (v.arith == DOT2) {
-        return (size_t)((px + CW - 1) / CW * CW) * py * 4;
+    if (v.arith == DOT2 || v.dtype == NRR_F32) {  // as the kernel's chunk-staged plane
+        const int pl = (px + CW - 1) / CW * CW * py;
+        return (size_t)(pl + (((pl / CW) & 1) ? 0 : CW)) * 4;
     }
     return ((size_t)px * py + ZPAD) * 4;
 }

@@ -33,10 +33,13 @@ struct BatchSelectSet {
     int32_t b, stride, gx, gy, gz;
     int32_t pad;
     int64_t ncand, k;
+    uint64_t *keys;  // scratch, ncand ranking keys
     int32_t *centers;
 };
+// max_cand: the largest ncand of the sets (sizes the key launch).
 hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
-                               const BatchSelectSet *sets, int nsets, hipStream_t stream);
+                               const BatchSelectSet *sets, int nsets, int64_t max_cand,
+                               hipStream_t stream);
 
 // ---------------------------------------------------------- window stats
 // Per-voxel statistics of the displaced block whose origin (lowest corner)

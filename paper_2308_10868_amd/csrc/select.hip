@@ -330,32 +330,78 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ ke
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Batched selection for small candidate grids: one workgroup per parameter
-// set keys its candidates (one thread per block), sorts (key descending,
-// grid index ascending) with a bitonic network in LDS, keeps the first K and
-// writes their centres in ascending grid index.  Same keys and tie rule as
-// the radix-select path, so the same blocks come out.
-__global__ __launch_bounds__(256) void k_select_batch(const void *__restrict__ vol, int is_u16,
-                                                      int nx, int ny,
-                                                      const BatchSelectSet *__restrict__ sets) {
+// Batched selection for small candidate grids.  The keys of every set's
+// candidates are computed first (one thread per candidate, grid y = set);
+// then one workgroup per set sorts (key descending, grid index ascending)
+// with a bitonic network in LDS, keeps the first K and writes their centres
+// in ascending grid index.  Same keys and tie rule as the radix-select path,
+// so the same blocks come out.
+// FP64 two-pass variance of nb values in order (the order of key_f32).
+__device__ inline uint64_t key_f32_seq(const float *v, int nb) {
+#pragma clang fp contract(off)
+    const double dn = (double)nb;
+    double sum = 0.0;
+    for (int o = 0; o < nb; ++o) sum += (double)v[o];
+    const double mean = sum / dn;
+    double ss = 0.0;
+    for (int o = 0; o < nb; ++o) {
+        const double d = (double)v[o] - mean;
+        ss += d * d;
+    }
+    return (uint64_t)__double_as_longlong(ss / dn);
+}
+
+// One wavefront per candidate: the wavefront copies the block to LDS, then
+// its first lane sums it in the fixed order (the result does not depend on
+// how the block was fetched).  Grid: (candidates / 4, sets).
+__global__ __launch_bounds__(256) void k_batch_keys(const void *__restrict__ vol, int is_u16,
+                                                    int nx, int ny,
+                                                    const BatchSelectSet *__restrict__ sets) {
+    constexpr int MAXV = 15 * 15 * 15;
+    __shared__ float blk[4][MAXV];
+    const BatchSelectSet &S = sets[blockIdx.y];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + wv;
+    if (i >= S.ncand) return;  // whole wavefront leaves together
+    const int b = S.b, nb = b * b * b;
+    const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
+    const int64_t x0 = (int64_t)ix * S.stride, y0 = (int64_t)iy * S.stride,
+                  z0 = (int64_t)iz * S.stride;
+    for (int o = lane; o < nb; o += 64) {
+        const int z = o / (b * b), y = (o / b) % b, x = o % b;
+        const int64_t at = ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0 + x;
+        blk[wv][o] = is_u16 ? (float)static_cast<const uint16_t *>(vol)[at]
+                            : static_cast<const float *>(vol)[at];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane != 0) return;
+    const float *v = blk[wv];
+    if (is_u16) {  // exact integers (12-bit values are exact in float)
+        uint64_t s = 0, q = 0;
+        for (int o = 0; o < nb; ++o) {
+            const uint64_t x = (uint64_t)v[o];
+            s += x;
+            q += x * x;
+        }
+        S.keys[i] = (uint64_t)nb * q - s * s;
+        return;
+    }
+    S.keys[i] = key_f32_seq(v, nb);
+}
+
+__global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__restrict__ sets) {
     __shared__ uint64_t key[kBatchCand];
     __shared__ uint16_t idx[kBatchCand];
     __shared__ uint8_t sel[kBatchCand];
-    __shared__ int wsum[4];
+    __shared__ int wsum[16];
     const BatchSelectSet S = sets[blockIdx.x];
     const int tid = threadIdx.x, n = (int)S.ncand;
     int n2 = 1;
     while (n2 < n) n2 <<= 1;
-    for (int i = tid; i < n2; i += 256) {
-        uint64_t kv = 0;  // padding sorts after every candidate (largest index)
-        if (i < n) {
-            const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
-            const int64_t x0 = (int64_t)ix * S.stride, y0 = (int64_t)iy * S.stride,
-                          z0 = (int64_t)iz * S.stride;
-            kv = is_u16 ? key_u16(static_cast<const uint16_t *>(vol), nx, ny, S.b, x0, y0, z0)
-                        : key_f32(static_cast<const float *>(vol), nx, ny, S.b, x0, y0, z0);
-        }
-        key[i] = kv;
+    for (int i = tid; i < n2; i += 1024) {
+        key[i] = i < n ? S.keys[i] : 0;  // padding sorts after every candidate (largest index)
         idx[i] = (uint16_t)(i < n ? i : 0xffff);
         if (i < n) sel[i] = 0;
     }
@@ -365,7 +411,7 @@ __global__ __launch_bounds__(256) void k_select_batch(const void *__restrict__ v
     };
     for (int k = 2; k <= n2; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < n2; i += 256) {
+            for (int i = tid; i < n2; i += 1024) {
                 const int l = i ^ j;
                 if (l > i && (((i & k) == 0) ? before(l, i) : before(i, l))) {
                     const uint64_t tk = key[i];
@@ -378,10 +424,10 @@ __global__ __launch_bounds__(256) void k_select_batch(const void *__restrict__ v
             }
             __syncthreads();
         }
-    for (int i = tid; i < S.k; i += 256) sel[idx[i]] = 1;
+    for (int i = tid; i < S.k; i += 1024) sel[idx[i]] = 1;
     __syncthreads();
     // ordered compaction: each thread owns a run of consecutive candidates
-    const int per = (n + 255) / 256, lo = min(n, tid * per), hi = min(n, lo + per);
+    const int per = (n + 1023) / 1024, lo = min(n, tid * per), hi = min(n, lo + per);
     int cnt = 0;
     for (int i = lo; i < hi; ++i) cnt += sel[i];
     int incl = cnt;  // inclusive scan over the wavefront, then over wavefronts
@@ -407,9 +453,13 @@ __global__ __launch_bounds__(256) void k_select_batch(const void *__restrict__ v
 }  // namespace
 
 hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
-                               const BatchSelectSet *sets, int nsets, hipStream_t stream) {
-    hipLaunchKernelGGL(k_select_batch, dim3((unsigned)nsets), dim3(256), 0, stream, vol,
-                       dtype == NRR_U16 ? 1 : 0, dims[0], dims[1], sets);
+                               const BatchSelectSet *sets, int nsets, int64_t max_cand,
+                               hipStream_t stream) {
+    if (max_cand > 0)
+        hipLaunchKernelGGL(k_batch_keys, dim3((unsigned)((max_cand + 3) / 4), (unsigned)nsets),
+                           dim3(256), 0, stream, vol, dtype == NRR_U16 ? 1 : 0, dims[0], dims[1],
+                           sets);
+    hipLaunchKernelGGL(k_select_batch, dim3((unsigned)nsets), dim3(1024), 0, stream, sets);
     return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 //
 // Layout of the outputs: dense [Oz][Oy][Ox] with O = dims - b + 1 (index =
 // lowest corner of the block).  Work decomposition: a workgroup owns a
-// 64 x 4 tile of (x, y) origins and a run of ZC origin planes; each input
+// 64 x 4 tile of (x, y) origins and a run of zc origin planes; each input
 // plane is staged in LDS (fetched two planes ahead) and summed along x
 // (sliding windows over 4-wide segments) then along y; the per-plane sums of
 // the last b planes sit in a small LDS ring, and the z sum slides exactly
@@ -28,7 +28,7 @@
 namespace nrr {
 namespace {
 
-constexpr int TX = 64, TY = 4, ZC = 32, MAXB = 15, SEG = 4;
+constexpr int TX = 64, TY = 4, ZC = 32, MAXB = 15, SEG = 4;  // ZC: most origin planes per run
 constexpr int PW = TX + MAXB - 1, PH = TY + MAXB - 1;
 constexpr int PATCH = PH * PW;
 constexpr int PER = (PATCH + 255) / 256;  // patch elements staged per thread
@@ -41,12 +41,12 @@ constexpr int PER = (PATCH + 255) / 256;  // patch elements staged per thread
 template <bool SLIDE, typename V, typename A, typename AQ, typename AS, typename AQQ,
           typename Src, typename Conv, typename Emit>
 __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int b,
-                                  int ox, int oy, int oz, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
+                                  int ox, int oy, int oz, int zc, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
                                   A *ringP, AQ *ringQ, Conv conv, Emit emit) {
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;  // output (tx, ty)
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
     const int ph = TY + b - 1, pw = TX + b - 1;
-    const int zend = min(z0 + ZC + b - 1, nz);  // input planes [z0, zend)
+    const int zend = min(z0 + zc + b - 1, nz);  // input planes [z0, zend)
     // this thread's patch elements: fixed offsets inside a plane
     int goff[PER];
     bool gok[PER];
@@ -141,7 +141,7 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
 
 __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ flt, int nx,
                                                    int ny, int nz, int b, int ox, int oy, int oz,
-                                                   StatU16 *__restrict__ out) {
+                                                   int zc, StatU16 *__restrict__ out) {
     __shared__ int32_t patch[2 * PATCH + 256];
     __shared__ int32_t rs[PH * TX];
     __shared__ uint32_t rq[PH * TX];
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ 
     uint32_t *ringQ = reinterpret_cast<uint32_t *>(dyn_u16 + (size_t)b * 256 * 4);
     const int64_t n = (int64_t)b * b * b;
     stats_body<true, int32_t, int32_t, uint32_t, int32_t, uint64_t>(
-        flt, nx, ny, nz, b, ox, oy, oz, patch, rs, rq, ringP, ringQ,
+        flt, nx, ny, nz, b, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
         [](uint16_t v) { return (int32_t)v - 2048; },
         [&](int64_t o, int32_t S, uint64_t QQ) {
             const int64_t var = n * (int64_t)QQ - (int64_t)S * S;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt, int nx, int ny,
-                                                   int nz, int b, int ox, int oy, int oz,
+                                                   int nz, int b, int ox, int oy, int oz, int zc,
                                                    StatF32 *__restrict__ out) {
     __shared__ float patch[2 * PATCH + 256];
     __shared__ double rs[PH * TX];
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
     double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)b * 256 * 8);
     const double n = (double)b * b * b;
     stats_body<false, float, double, double, double, double>(
-        flt, nx, ny, nz, b, ox, oy, oz, patch, rs, rq, ringP, ringQ, [](float v) { return v; },
+        flt, nx, ny, nz, b, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, [](float v) { return v; },
         [&](int64_t o, double S, double QQ) {
             const double nq = n * QQ;
             const double var = nq - S * S;
@@ -235,11 +235,17 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
                         void *workspace, hipStream_t stream) {
     StatsLayout L = stats_layout(dtype, dims, block);
     char *ws = static_cast<char *>(workspace);
-    dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + ZC - 1) / ZC);
+    // origin planes per workgroup: ZC, fewer when that leaves the device with
+    // too few workgroups (small volumes), never below 4
+    const int64_t per_slab = (int64_t)((L.ox + TX - 1) / TX) * ((L.oy + TY - 1) / TY);
+    const int64_t slabs = (512 + per_slab - 1) / per_slab;
+    int zc = (int)((L.oz + slabs - 1) / slabs);
+    zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
+    dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
     if (dtype == NRR_U16) {
         hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)block * 256 * 8, stream,
                            static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], block,
-                           L.ox, L.oy, L.oz, reinterpret_cast<StatU16 *>(ws));
+                           L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws));
         const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
         const int64_t groups = (nvox + 1023) / 1024;
         hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
@@ -248,7 +254,7 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     } else
         hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)block * 256 * 16, stream,
                            static_cast<const float *>(flt), dims[0], dims[1], dims[2], block,
-                           L.ox, L.oy, L.oz, reinterpret_cast<StatF32 *>(ws));
+                           L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
     return hipGetLastError();
 }
 
