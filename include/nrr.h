@@ -245,6 +245,73 @@ nrr_status nrr_batch_plan_run(nrr_batch_plan *plan, void *stream);
 
 nrr_status nrr_batch_plan_destroy(nrr_batch_plan *plan);
 
+/* ------------------------------------------------------------------ serving
+ * A registration server for requests that arrive over time (the paper's
+ * intra-operative setting: a registration must finish within the procedure,
+ * while new scans keep arriving).  A request is one registration's block
+ * matching: a volume pair and (block, stride, fraction, window); its result
+ * is what nrr_select_blocks + nrr_block_match give for it.
+ *
+ * The server owns `device_bytes` of device memory (one allocation, made at
+ * creation) and `slots` HIP streams.  A scheduler thread admits waiting
+ * requests in arrival order as soon as a slot is free and the request's
+ * device footprint (both volumes, selection and search workspaces, outputs:
+ * nrr_request_footprint) fits in the free memory; a later request may pass
+ * one that waits for memory if it fits, at most 8 times per waiting request.
+ * Admitted requests run concurrently, each on its slot's stream: upload,
+ * selection, window statistics, search, download.  Their memory returns to
+ * the server when they complete.  Results do not depend on what else runs.
+ *
+ *  nrr_request.ref/flt   host or device volumes, dims[2]*dims[1]*dims[0]
+ *                        voxels of dtype; read during the request's upload,
+ *                        so they must stay unchanged until it completes.
+ *  centers/disp/ncc/conf host or device outputs of >= K rows (K from
+ *                        nrr_select_count; capacity = their rows), written
+ *                        when the request completes.  Page-locked host
+ *                        memory lets the copies overlap other work.  NULL
+ *                        outputs are not copied out.
+ *
+ * nrr_server_submit (any host thread) validates and queues a request and
+ * returns its ticket; INVALID_ARG / BUFFER_TOO_SMALL as the plain calls,
+ * UNSUPPORTED when the footprint exceeds the server's memory or the search
+ * is unsupported.  nrr_server_poll reports a ticket's state (0 queued,
+ * 1 running, 2 done, 3 failed), its K, device bytes and times (queued, run,
+ * submit-to-done) without blocking; nrr_server_wait blocks until it is done
+ * and returns its status.  nrr_server_destroy finishes every submitted
+ * request, then frees the server's memory and streams. */
+typedef struct {
+    const void *ref, *flt;
+    nrr_dtype dtype;
+    int32_t dims[3];
+    int32_t block, stride, window;
+    double fraction;
+    int32_t *centers, *disp;
+    float *ncc, *conf;
+    int64_t capacity;
+} nrr_request;
+
+typedef struct {
+    int32_t state, status;
+    int64_t k, device_bytes;
+    double queued_ms, run_ms, total_ms;
+} nrr_request_info;
+
+typedef struct {
+    int64_t device_bytes, peak_bytes, used_bytes;
+    int32_t slots, max_running;
+    int64_t submitted, admitted, completed, pending;
+} nrr_server_info;
+
+typedef struct nrr_server nrr_server;
+
+nrr_status nrr_request_footprint(const nrr_request *request, size_t *bytes);
+nrr_status nrr_server_create(size_t device_bytes, int32_t slots, nrr_server **server);
+nrr_status nrr_server_submit(nrr_server *server, const nrr_request *request, int64_t *ticket);
+nrr_status nrr_server_poll(nrr_server *server, int64_t ticket, nrr_request_info *info);
+nrr_status nrr_server_wait(nrr_server *server, int64_t ticket, nrr_request_info *info);
+nrr_status nrr_server_stats(nrr_server *server, nrr_server_info *info);
+nrr_status nrr_server_destroy(nrr_server *server);
+
 /* ------------------------------------------------------------- diagnostics */
 
 /* Static string for a status code. */

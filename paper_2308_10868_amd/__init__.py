@@ -37,6 +37,8 @@ __all__ = [
     "ParamSet",
     "batch_layout",
     "BatchPlan",
+    "Server",
+    "request_footprint",
     "U16",
     "F32",
 ]
@@ -60,6 +62,34 @@ class ParamSet(ctypes.Structure):
     """One parameter set of the batched search (block, window, stride, fraction)."""
     _fields_ = [("block", ctypes.c_int32), ("window", ctypes.c_int32), ("stride", ctypes.c_int32),
                 ("fraction", ctypes.c_double)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("ref", ctypes.c_void_p), ("flt", ctypes.c_void_p), ("dtype", ctypes.c_int),
+                ("dims", ctypes.c_int32 * 3), ("block", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("window", ctypes.c_int32), ("fraction", ctypes.c_double),
+                ("centers", ctypes.c_void_p), ("disp", ctypes.c_void_p), ("ncc", ctypes.c_void_p),
+                ("conf", ctypes.c_void_p), ("capacity", ctypes.c_int64)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("k", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("queued_ms", ctypes.c_double),
+                ("run_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _ServerInfo(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("used_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("max_running", ctypes.c_int32), ("submitted", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("pending", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class NrrError(RuntimeError):
@@ -104,6 +134,13 @@ def load():
                                        P]),
         "nrr_batch_plan_run": (st, [P, P]),
         "nrr_batch_plan_destroy": (st, [P]),
+        "nrr_request_footprint": (st, [P, P]),
+        "nrr_server_create": (st, [SZ, I32, P]),
+        "nrr_server_submit": (st, [P, P, P]),
+        "nrr_server_poll": (st, [P, I64, P]),
+        "nrr_server_wait": (st, [P, I64, P]),
+        "nrr_server_stats": (st, [P, P]),
+        "nrr_server_destroy": (st, [P]),
         "nrr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "nrr_last_error": (ctypes.c_char_p, []),
         "nrr_version": (I32, []),
@@ -364,6 +401,115 @@ class BatchPlan:
     def close(self):
         if getattr(self, "_h", None) is not None:
             load().nrr_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+
+def _host_or_dev_info(t):
+    torch = _torch()
+    if t.dim() != 3 or not t.is_contiguous():
+        raise NrrError(1, "volumes must be contiguous [nz, ny, nx] tensors")
+    if t.dtype == torch.uint16:
+        dt = U16
+    elif t.dtype == torch.float32:
+        dt = F32
+    else:
+        raise NrrError(1, "volume dtype must be uint16 or float32, got %s" % t.dtype)
+    nz, ny, nx = t.shape
+    return dt, (nx, ny, nz)
+
+
+def _make_request(ref, flt, block, stride, window, fraction, outs=None):
+    dt, dims = _host_or_dev_info(ref)
+    dt2, dims2 = _host_or_dev_info(flt)
+    if dt != dt2 or dims != dims2:
+        raise NrrError(1, "ref and flt must share dtype and shape")
+    r = _Request()
+    r.ref, r.flt, r.dtype = ref.data_ptr(), flt.data_ptr(), dt
+    r.dims[:] = list(dims)
+    r.block, r.stride, r.window, r.fraction = int(block), int(stride), int(window), float(fraction)
+    if outs is not None:
+        c, d, n, f = outs
+        r.centers, r.disp, r.ncc, r.conf = c.data_ptr(), d.data_ptr(), n.data_ptr(), f.data_ptr()
+        r.capacity = c.shape[0]
+    return r, dt, dims
+
+
+def request_footprint(ref, flt, block: int, stride: int, window: int, fraction: float) -> int:
+    """Device bytes one served request occupies while it runs."""
+    r, _, _ = _make_request(ref, flt, block, stride, window, fraction)
+    nb = ctypes.c_size_t()
+    _check(load().nrr_request_footprint(ctypes.byref(r), ctypes.byref(nb)))
+    return nb.value
+
+
+class Job:
+    """One submitted registration: poll()/wait() give its state and times;
+    after wait(), centers/disp/ncc/conf hold its results (host tensors in
+    page-locked memory, or the device tensors given at submission)."""
+
+    def __init__(self, server, ticket, keep, outs, k):
+        self.server, self.ticket, self._keep = server, ticket, keep
+        self.centers, self.disp, self.ncc, self.conf = [o[:k] for o in outs]
+        self.k = k
+
+    def poll(self):
+        info = _RequestInfo()
+        _check(load().nrr_server_poll(self.server._h, self.ticket, ctypes.byref(info)))
+        return info.as_dict()
+
+    def wait(self):
+        info = _RequestInfo()
+        st = load().nrr_server_wait(self.server._h, self.ticket, ctypes.byref(info))
+        _check(st)
+        self._keep = None
+        return info.as_dict()
+
+
+class Server:
+    """Registration server: admits requests as slots and device memory free
+    up (continuous batching); see nrr_server_create in include/nrr.h."""
+
+    def __init__(self, device_bytes: int = 8 << 30, slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(load().nrr_server_create(int(device_bytes), int(slots), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, ref, flt, block: int, stride: int, window: int, fraction: float,
+               out=None) -> Job:
+        """Queue one registration.  `ref`/`flt` are [nz, ny, nx] host (ideally
+        page-locked) or device tensors, kept alive until the job completes.
+        Results go to `out` = (centers, disp, ncc, conf) tensors of >= K rows
+        if given, else to new page-locked host tensors."""
+        torch = _torch()
+        dt, dims = _host_or_dev_info(ref)
+        k = select_count(dims, block, stride, fraction)
+        if out is None:
+            rows = max(k, 1)
+            out = (torch.empty((rows, 3), dtype=torch.int32, pin_memory=True),
+                   torch.empty((rows, 3), dtype=torch.int32, pin_memory=True),
+                   torch.empty(rows, dtype=torch.float32, pin_memory=True),
+                   torch.empty(rows, dtype=torch.float32, pin_memory=True))
+        r, _, _ = _make_request(ref, flt, block, stride, window, fraction, out)
+        t = ctypes.c_int64()
+        _check(load().nrr_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return Job(self, t.value, (ref, flt), out, k)
+
+    def stats(self):
+        info = _ServerInfo()
+        _check(load().nrr_server_stats(self._h, ctypes.byref(info)))
+        return info.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().nrr_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

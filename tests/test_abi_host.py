@@ -171,3 +171,22 @@ def test_param_sets_generator():
     for b, w, s, f in a:
         assert b in (5, 7, 9) and w in (5, 8, 12) and s == b and f in (0.05, 0.1, 0.25, 0.5)
     assert len({(b, w, f) for b, w, s, f in a}) > 10
+
+
+def test_request_footprint_closed_form(lib):
+    import torch
+
+    import paper_2308_10868_amd as nrr
+
+    ref = torch.zeros((48, 56, 64), dtype=torch.uint16)
+    flt = torch.zeros((48, 56, 64), dtype=torch.uint16)
+    fp = nrr.request_footprint(ref, flt, 7, 7, 5, 0.25)
+    up = lambda v: (v + 255) // 256 * 256
+    dims = (64, 56, 48)
+    k = nrr.select_count(dims, 7, 7, 0.25)
+    vb = 64 * 56 * 48 * 2
+    want = (2 * up(vb) + up(nrr.select_workspace_bytes(dims, 7, 7))
+            + up(nrr.match_workspace_bytes(nrr.U16, dims, 7)) + 2 * up(12 * k) + 2 * up(4 * k))
+    assert fp == want
+    with pytest.raises(nrr.NrrError):
+        nrr.request_footprint(ref, flt, 6, 7, 5, 0.25)
