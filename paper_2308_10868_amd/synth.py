@@ -286,3 +286,27 @@ def gen_param_sets(n: int = 32, seed: int = 1, blocks=(5, 7, 9), windows=(5, 8, 
     w = r.choice(np.asarray(windows), size=n)
     f = r.choice(np.asarray(fractions, dtype=np.float64), size=n)
     return [(int(b[i]), int(w[i]), int(b[i]), float(f[i])) for i in range(n)]
+
+
+SERVING_SIZES = ((128, 128, 128), (192, 192, 96), (256, 256, 124), (384, 384, 160))
+
+
+def gen_serving_requests(n: int, seed: int = 4, rate_hz: float = 4.0, pool_seeds: int = 2):
+    """Registration requests for the serving workload: Poisson arrivals at
+    `rate_hz` (exponential gaps), volume size uniform over SERVING_SIZES,
+    window uniform in 5..15, block uniform in {5, 7, 9} (grid stride = block),
+    fraction uniform in [0.1, 0.3].  Each request names the volume pair it
+    registers by (size, volume seed), the seed drawn from `pool_seeds` values
+    so a benchmark can generate the pairs once (gen_blobs_u16 at that size)."""
+    (r,) = _streams(seed, 1)
+    gaps = r.exponential(1.0 / rate_hz, size=n)
+    out = []
+    t = 0.0
+    for i in range(n):
+        t += float(gaps[i])
+        b = int(r.choice([5, 7, 9]))
+        out.append({"arrival_s": t, "size": SERVING_SIZES[int(r.integers(0, len(SERVING_SIZES)))],
+                    "block": b, "stride": b, "window": int(r.integers(5, 16)),
+                    "fraction": float(r.uniform(0.1, 0.3)),
+                    "volume_seed": int(r.integers(0, pool_seeds))})
+    return out
