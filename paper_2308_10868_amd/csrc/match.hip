@@ -33,6 +33,7 @@
 //    volumes, so it does not inherit the ranking arithmetic's rounding.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
@@ -445,7 +446,7 @@ __device__ __attribute__((always_inline)) inline void dot2_cross(
 // smallest shift index (irow + j*side + i).  Displacements past the valid
 // extents (nvx, nvy) are masked without a branch.  For 12-bit data the staged
 // F sums are offset by `fshift` from the table's.
-template <bool U16, int RX, int RY, typename Rec, typename XT, typename KeyT>
+template <bool U16, bool SHIFT, int RX, int RY, typename Rec, typename XT, typename KeyT>
 __device__ __attribute__((always_inline)) inline void rank_tile(
     const Rec (&rec)[RX][RY], const XT (&xacc)[RX][RY], double dN, double tsum, double fshift,
     float c, int nvx, int nvy, int irow, int side, KeyT &tk, int &ti) {
@@ -457,7 +458,8 @@ __device__ __attribute__((always_inline)) inline void rank_tile(
             KeyT key;
             if constexpr (U16) {
                 const double cov =
-                    __builtin_fma(dN, (double)xacc[i][j], -tsum * ((double)rec[i][j].s + fshift));
+                    __builtin_fma(dN, (double)xacc[i][j],
+                                  -tsum * (SHIFT ? (double)rec[i][j].s + fshift : (double)rec[i][j].s));
                 key = (float)cov * rec[i][j].r;
             } else {
                 const double cov = dN * (double)xacc[i][j] - tsum * (rec[i][j].s - dN * (double)c);
@@ -717,7 +719,7 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
             const double tsum = ARITH == DOT2 ? (double)sT : sTc;  // sum of the staged T
             KeyT tk = -INFINITY;
             int ti = INT_MAX;
-            rank_tile<U16>(rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX, g.dy - ty * RY, irow,
+            rank_tile<U16, ARITH != DOT2>(rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX, g.dy - ty * RY, irow,
                            side, tk, ti);
             better(bk, bi, tk, ti);
         }
@@ -919,10 +921,25 @@ size_t window_plane_bytes(const Variant &v, int w) {
     return ((size_t)px * py + ZPAD) * 4;
 }
 
+// Wavefront-rounds of one block's search with z-chunks of cz displacement
+// planes (the last chunk takes the rest), plus half a round per extra chunk
+// for its staging and barriers.  Idle wavefronts of a round skip the tiles.
+double chunk_rounds(const Variant &v, int d, int cz) {
+    const int per_dz = ((d + v.rx - 1) / v.rx) * ((d + v.ry - 1) / v.ry);
+    double r = 0.0;
+    for (int z0 = 0; z0 < d; z0 += cz) {
+        const int tiles = per_dz * std::min(cz, d - z0);
+        r += std::ceil(tiles / 64.0) + (z0 > 0 ? 0.5 : 0.0);
+    }
+    return r;
+}
+
 // z-chunk and LDS size: the whole window if it fits in `target` bytes (two
 // workgroups per CU), else the largest balanced chunk of displacement planes
 // that still fits in `target`, else the largest that fits in `limit`.
-// Re-staging the b-1 overlap planes of each chunk is cheap next to the search.
+// (Balanced chunks keep the workgroup's LDS small: on the 256x256x124 search,
+// 11 + 10 planes with three workgroups per CU beat 12 + 9 with two, although
+// the latter packs the tiles into fewer wavefront-rounds.)
 bool plan_variant(const Variant &v, int w, size_t limit, size_t target, Plan *out) {
     const int d = 2 * w + 1;
     const size_t fixed = t_table_bytes(v) + 2048;  // + static shared and slack
@@ -946,8 +963,7 @@ bool plan_variant(const Variant &v, int w, size_t limit, size_t target, Plan *ou
 double plan_cost(const Plan &pl, int w) {
     const Variant &v = *pl.v;
     const int d = 2 * w + 1;
-    const double tiles = (double)((d + v.rx - 1) / v.rx) * ((d + v.ry - 1) / v.ry) * pl.cz;
-    const double rounds = std::ceil(tiles / v.nt) * ((d + pl.cz - 1) / pl.cz);
+    const double rounds = chunk_rounds(v, d, pl.cz) * 64.0 / v.nt;
     const double planes = v.arith == DOT2 ? (v.b + 1) / 2 : v.b;
     // instructions per tile: multiply-adds (dot2 issues at half the FMA rate)
     const double per = planes * v.rx * v.ry * v.b * v.b * (v.arith == DOT2 ? 2.0 : 1.0) +
@@ -1001,9 +1017,8 @@ bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, const T
             if (pass == 0 && !shape_matches(v, *force)) continue;
             Plan pl;
             if (!plan_variant(v, w, limit, limit / 2, &pl)) continue;
-            if (pass == 0 && force->cz > 0 && force->cz < pl.cz) {
-                const int d = 2 * w + 1, nch = (d + force->cz - 1) / force->cz;
-                pl.cz = (d + nch - 1) / nch;
+            if (pass == 0 && force->cz > 0 && force->cz < pl.cz) {  // a smaller chunk, as given
+                pl.cz = force->cz;
                 pl.lds = t_table_bytes(v) + (size_t)(pl.cz + v.b - 1) * window_plane_bytes(v, w);
             }
             const double c = plan_cost(pl, w);
@@ -1019,13 +1034,15 @@ bool choose_with(nrr_dtype dtype, int b, int w, size_t limit, int arith, const T
 }
 
 // Shape priority: an explicit one (the tuner's trials), the environment
-// overrides, the tuned table, then the cost model.  NRR_ARITH=dot2|fma
-// restricts 12-bit volumes to one arithmetic form.
+// overrides, the tuned table, then the cost model.  12-bit volumes use the
+// exact dot2 form when a shape has it (it measures faster than FMA on every
+// shape tried); NRR_ARITH=dot2|fma restricts them to one form.
 bool choose(nrr_dtype dtype, int b, int w, size_t limit, const TileShape *force, Plan *best) {
     TileShape sh;
     if (!force && shape_from_env(&sh)) force = &sh;
     if (!force && tuned_shape(dtype, b, w, &sh)) force = &sh;
-    const int pref = arith_preference();
+    int pref = arith_preference();
+    if (pref < 0 && dtype == NRR_U16 && !(force && force->arith >= 0)) pref = DOT2;
     if (pref >= 0 && choose_with(dtype, b, w, limit, pref, force, best)) return true;
     return choose_with(dtype, b, w, limit, -1, force, best);
 }
