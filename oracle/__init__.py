@@ -48,6 +48,8 @@ def _load():
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         lib.oracle_select.restype = i64
         lib.oracle_select.argtypes = [P, ctypes.c_int, P, i32, i32, f64, P, P, i64]
+        lib.oracle_select_ex.restype = i64
+        lib.oracle_select_ex.argtypes = [P, ctypes.c_int, P, i32, i32, f64, P, i32, P, P, i64]
         lib.oracle_block_variance.restype = ctypes.c_int
         lib.oracle_block_variance.argtypes = [P, ctypes.c_int, P, i32, i32, P, P]
         lib.oracle_match.restype = ctypes.c_int
@@ -123,6 +125,29 @@ def select(vol: np.ndarray, block: int, stride: int, fraction: float):
                               _ptr(out), _ptr(var), cap)
     if k < 0:
         raise ValueError("oracle_select rejected the arguments (%d)" % k)
+    return out[:k].copy(), var[:k].copy()
+
+
+def select_ex(vol: np.ndarray, block: int, stride: int, fraction: float, mask=None,
+              connectivity: int = 0):
+    """Selection with a candidate mask (uint8 volume, nonzero = candidate
+    centre allowed) and a connectivity pattern (0, 6, 18, 26): the taken
+    centres int32[k, 3] in ascending grid index, and their variances."""
+    vol, dt = _vol(vol)
+    dims = _dims(vol)
+    n = int(np.prod(grid_shape(dims, block, stride)))
+    cap = max(1, n)
+    out = np.empty((cap, 3), dtype=np.int32)
+    var = np.empty(cap, dtype=np.float64)
+    mp = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert mask.shape == vol.shape
+        mp = _ptr(mask)
+    k = _load().oracle_select_ex(_ptr(vol), dt, _ptr(dims), block, stride, float(fraction), mp,
+                                 int(connectivity), _ptr(out), _ptr(var), cap)
+    if k < 0:
+        raise ValueError("oracle_select_ex rejected the arguments (%d)" % k)
     return out[:k].copy(), var[:k].copy()
 
 

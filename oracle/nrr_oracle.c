@@ -181,6 +181,93 @@ int64_t oracle_select(const void *vol, int dtype, const int32_t dims[3], int32_t
     return k;
 }
 
+/*
+ * Selection with the variants of the "Parallel feature selection" paragraph:
+ * a connectivity pattern that keeps selected blocks apart, and candidates
+ * restricted to a region (the intracranial cavity in the paper; here any
+ * 0/1 mask).
+ *
+ *  - mask (may be NULL): uint8 volume like `vol`; a candidate takes part iff
+ *    the mask is nonzero at its centre.  N = number of such candidates and
+ *    K = floor(0.5 + N * fraction).
+ *  - connectivity 0, 6, 18 or 26: candidates are visited in rank order
+ *    (variance descending, grid index ascending); one is taken unless a
+ *    candidate adjacent to it on the grid is already taken, where adjacent
+ *    means one grid step along one axis (6, faces), along at most two axes
+ *    (18, faces and edges) or along up to three (26, also vertices); the
+ *    visit stops once K are taken (fewer when the candidates run out).
+ *  - output: the taken centres in ascending grid index (and variances).
+ * Returns the number taken, -1 on bad arguments, -2 if capacity < K.
+ */
+int64_t oracle_select_ex(const void *vol, int dtype, const int32_t dims[3], int32_t b,
+                         int32_t stride, double fraction, const uint8_t *mask,
+                         int32_t connectivity, int32_t *out_centers, double *out_var,
+                         int64_t capacity) {
+    int32_t grid[3];
+    if (b < 1 || (b % 2) == 0 || oracle_grid_shape(dims, b, stride, grid)) return -1;
+    if (!(fraction > 0.0) || fraction > 1.0) return -1;
+    if (connectivity != 0 && connectivity != 6 && connectivity != 18 && connectivity != 26)
+        return -1;
+    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    const int32_t h = (b - 1) / 2;
+    double *key = (double *)malloc(sizeof(double) * n);
+    double *var = (double *)malloc(sizeof(double) * n);
+    ranked_t *r = (ranked_t *)malloc(sizeof(ranked_t) * n);
+    unsigned char *taken = (unsigned char *)calloc((size_t)n, 1);
+    int64_t *chosen = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    oracle_block_variance(vol, dtype, dims, b, stride, key, var);
+    int64_t m = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1],
+                      gz = g / ((int64_t)grid[0] * grid[1]);
+        const int64_t cx = gx * stride + h, cy = gy * stride + h, cz = gz * stride + h;
+        if (mask && !mask[(cz * dims[1] + cy) * (int64_t)dims[0] + cx]) continue;
+        r[m].key = key[g];
+        r[m].idx = g;
+        ++m;
+    }
+    const int64_t k = oracle_select_count(m, fraction);
+    if (k > capacity) {
+        free(key), free(var), free(r), free(taken), free(chosen);
+        return -2;
+    }
+    qsort(r, (size_t)m, sizeof(ranked_t), cmp_rank);
+    int64_t got = 0;
+    for (int64_t i = 0; i < m && got < k; ++i) {
+        const int64_t g = r[i].idx;
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1],
+                      gz = g / ((int64_t)grid[0] * grid[1]);
+        int blocked = 0;
+        for (int dz = -1; dz <= 1 && !blocked && connectivity; ++dz)
+            for (int dy = -1; dy <= 1 && !blocked; ++dy)
+                for (int dx = -1; dx <= 1 && !blocked; ++dx) {
+                    const int steps = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (steps == 0) continue;
+                    if (connectivity == 6 && steps > 1) continue;
+                    if (connectivity == 18 && steps > 2) continue;
+                    const int64_t x = gx + dx, y = gy + dy, z = gz + dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= grid[0] || y >= grid[1] || z >= grid[2])
+                        continue;
+                    if (taken[(z * grid[1] + y) * grid[0] + x]) blocked = 1;
+                }
+        if (blocked) continue;
+        taken[g] = 1;
+        chosen[got++] = g;
+    }
+    qsort(chosen, (size_t)got, sizeof(int64_t), cmp_i64);
+    for (int64_t i = 0; i < got; ++i) {
+        const int64_t g = chosen[i];
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1],
+                      gz = g / ((int64_t)grid[0] * grid[1]);
+        out_centers[3 * i + 0] = (int32_t)(gx * stride + h);
+        out_centers[3 * i + 1] = (int32_t)(gy * stride + h);
+        out_centers[3 * i + 2] = (int32_t)(gz * stride + h);
+        if (out_var) out_var[i] = var[g];
+    }
+    free(key), free(var), free(r), free(taken), free(chosen);
+    return got;
+}
+
 /* Is the block of edge b centred at (cx,cy,cz) inside the volume? */
 static int block_inside(const int32_t dims[3], int32_t h, int64_t cx, int64_t cy, int64_t cz) {
     return cx - h >= 0 && cy - h >= 0 && cz - h >= 0 && cx + h <= dims[0] - 1 &&

@@ -41,6 +41,54 @@ def select(vol: np.ndarray, block: int, stride: int, fraction: float) -> np.ndar
     return np.stack([ox[gx] + h, oy[gy] + h, oz[gz] + h], axis=1).astype(np.int32)
 
 
+def select_ex(vol: np.ndarray, block: int, stride: int, fraction: float, mask=None,
+              connectivity: int = 0) -> np.ndarray:
+    """Greedy selection in rank order with a candidate mask and a connectivity
+    pattern, written independently of the C oracle (small grids only)."""
+    nz, ny, nx = vol.shape
+    ox, oy, oz = (grid_origins(n, block, stride) for n in (nx, ny, nz))
+    blocks = sliding_window_view(vol, (block, block, block))[np.ix_(oz, oy, ox)]
+    blocks = blocks.reshape(len(oz) * len(oy) * len(ox), -1)
+    if vol.dtype == np.uint16:
+        v = blocks.astype(np.int64)
+        score = block ** 3 * (v * v).sum(axis=1) - v.sum(axis=1) ** 2
+    else:
+        score = blocks.astype(np.float64).var(axis=1)
+    h = (block - 1) // 2
+    G = (len(ox), len(oy), len(oz))
+    cand = []
+    for g in range(score.shape[0]):
+        gz, rem = divmod(g, G[0] * G[1])
+        gy, gx = divmod(rem, G[0])
+        if mask is None or mask[oz[gz] + h, oy[gy] + h, ox[gx] + h]:
+            cand.append(g)
+    k = min(len(cand), max(0, math.floor(0.5 + len(cand) * fraction)))
+    cand.sort(key=lambda g: (-score[g], g))
+    limit = {0: 0, 6: 1, 18: 2, 26: 3}[connectivity]
+    taken = set()
+    for g in cand:
+        if len(taken) == k:
+            break
+        gz, rem = divmod(g, G[0] * G[1])
+        gy, gx = divmod(rem, G[0])
+        near = False
+        for q in taken:
+            qz, r2 = divmod(q, G[0] * G[1])
+            qy, qx = divmod(r2, G[0])
+            d = (abs(qx - gx), abs(qy - gy), abs(qz - gz))
+            if max(d) == 1 and sum(d) <= limit:
+                near = True
+                break
+        if not near:
+            taken.add(g)
+    out = []
+    for g in sorted(taken):
+        gz, rem = divmod(g, G[0] * G[1])
+        gy, gx = divmod(rem, G[0])
+        out.append((ox[gx] + h, oy[gy] + h, oz[gz] + h))
+    return np.asarray(out, dtype=np.int32).reshape(-1, 3)
+
+
 def surface(ref: np.ndarray, flt: np.ndarray, center, block: int, window: int) -> np.ndarray:
     """NCC over [-W, W]^3 indexed [dz+W, dy+W, dx+W]; NaN where invalid."""
     h = (block - 1) // 2

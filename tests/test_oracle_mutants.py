@@ -35,6 +35,22 @@ MUTANTS = {
                             "int32_t h = (b - 1) / 2 + 1;\n    int64_t nb = (int64_t)b * b * b;\n#pragma omp parallel\n    {\n        double *tc = (double *)malloc(sizeof(double) * nb);\n        double *fb = (double *)malloc(sizeof(double) * nb);\n#pragma omp for schedule(dynamic, 1)\n        for (int64_t k = 0; k < n; ++k) {\n            int64_t cx"),
 }
 
+# mistakes in the selection variants, caught by their own pin file
+MUTANTS_EX = {
+    "edges_counted_as_vertices": ("if (connectivity == 18 && steps > 2) continue;",
+                                  "if (connectivity == 18 && steps > 3) continue;"),
+    "mask_ignored": ("if (mask && !mask[(cz * dims[1] + cy) * (int64_t)dims[0] + cx]) continue;",
+                     "if (0) continue;"),
+    "count_over_all_candidates": ("const int64_t k = oracle_select_count(m, fraction);",
+                                  "const int64_t k = oracle_select_count(n, fraction);"),
+    "taken_not_marked": ("taken[g] = 1;\n        chosen[got++] = g;", "chosen[got++] = g;"),
+    "faces_skip_z": ("for (int dz = -1; dz <= 1 && !blocked && connectivity; ++dz)",
+                     "for (int dz = 0; dz <= 0 && !blocked && connectivity; ++dz)"),
+}
+PIN_FILES = {name: "test_oracle_pins.py" for name in MUTANTS}
+PIN_FILES.update({name: "test_oracle_select_ex.py" for name in MUTANTS_EX})
+MUTANTS.update(MUTANTS_EX)
+
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(tmp_path, name):
@@ -49,6 +65,6 @@ def test_pins_catch_planted_mistake(tmp_path, name):
                            "-std=c11", str(csrc), "-o", str(lib), "-lm"])
     env = dict(os.environ, NRR_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", PIN_FILES[name])],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "pins did not catch mutant %s:\n%s" % (name, r.stdout[-2000:])
