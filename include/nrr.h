@@ -116,6 +116,33 @@ nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dim
                              int64_t capacity, int64_t *k_out, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/* Selection variants of the same paragraph: candidates restricted to a
+ * region, and a connectivity pattern that keeps selected blocks apart.
+ *
+ *  mask          device, optional (NULL: every candidate): uint8 volume of
+ *                dims; a candidate takes part iff the mask is nonzero at its
+ *                centre.  N = number of candidates taking part, and the count
+ *                is K = floor(0.5 + N * fraction).
+ *  connectivity  0, 6, 18 or 26.  Candidates are visited in rank order (as
+ *                nrr_select_blocks ranks them) and one is taken unless a
+ *                candidate adjacent to it on the grid is already taken:
+ *                adjacent = one grid step along one axis (6), along up to two
+ *                axes (18) or up to three (26).  The visit stops at K taken
+ *                (fewer when the candidates run out).  0: plain top-K among
+ *                the candidates taking part.
+ *  centers       device int32 [capacity][3]: the taken centres in ascending
+ *                grid index; capacity >= floor(0.5 + grid count * fraction)
+ *                (the count without a mask).
+ *  k_device      device int64: receives the number taken (asynchronously).
+ *  workspace     device, >= nrr_select_workspace_bytes().
+ * Errors: INVALID_ARG (as nrr_select_blocks; connectivity not 0/6/18/26),
+ * BUFFER_TOO_SMALL, UNSUPPORTED (more than 24576 candidates), HIP. */
+nrr_status nrr_select_blocks_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                int32_t block, int32_t stride, double fraction,
+                                const uint8_t *mask, int32_t connectivity, int32_t *centers,
+                                int64_t capacity, int64_t *k_device, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 /* ----------------------------------------------------------------- matching
  * Exhaustive NCC block matching (NCC equation and the GPU block-matching
  * algorithm: every displacement of the window is evaluated and the maximum

@@ -29,6 +29,7 @@ __all__ = [
     "match_workspace_bytes",
     "match_supported",
     "select_blocks",
+    "select_blocks_ex",
     "block_match",
     "window_stats",
     "tune_match",
@@ -122,6 +123,8 @@ def load():
         "nrr_match_supported": (st, [ctypes.c_int, I32, I32]),
         "nrr_select_blocks": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P, SZ, P]),
         "nrr_block_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, P]),
+        "nrr_select_blocks_ex": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I32, P, I64, P, P, SZ,
+                                      P]),
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
@@ -243,6 +246,33 @@ def select_blocks(vol, block: int, stride: int, fraction: float, workspace=None)
                                  ctypes.byref(kout), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream(vol)))
     return out[:kout.value]
+
+
+def select_blocks_ex(vol, block: int, stride: int, fraction: float, mask=None,
+                     connectivity: int = 0, workspace=None):
+    """Selection restricted to a mask (uint8 device tensor like `vol`; nonzero
+    = candidate centre allowed) with a connectivity pattern (0, 6, 18, 26).
+    Returns int32 [k, 3] centres in ascending grid index.  Synchronises the
+    stream to read k."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(vol)
+    kmax = select_count(dims, block, stride, fraction)
+    out = torch.empty((max(kmax, 1), 3), dtype=torch.int32, device=vol.device)
+    kd = torch.zeros(1, dtype=torch.int64, device=vol.device)
+    ws = _workspace(select_workspace_bytes(dims, block, stride), vol.device, workspace)
+    mp = None
+    if mask is not None:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(vol.shape) \
+                or not mask.is_contiguous() or mask.device != vol.device:
+            raise NrrError(1, "mask must be a contiguous uint8 tensor shaped like vol")
+        mp = ctypes.c_void_p(mask.data_ptr())
+    _check(lib.nrr_select_blocks_ex(ctypes.c_void_p(vol.data_ptr()), dt, _dims3(dims), block,
+                                    stride, float(fraction), mp, int(connectivity),
+                                    ctypes.c_void_p(out.data_ptr()), out.shape[0],
+                                    ctypes.c_void_p(kd.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel(), _stream(vol)))
+    return out[:int(kd.item())]
 
 
 def window_stats(flt, block: int, workspace=None):

@@ -166,6 +166,40 @@ nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dim
     return hip_status(e, "nrr_select_blocks launch");
 }
 
+nrr_status nrr_select_blocks_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                int32_t block, int32_t stride, double fraction,
+                                const uint8_t *mask, int32_t connectivity, int32_t *centers,
+                                int64_t capacity, int64_t *k_device, void *workspace,
+                                size_t workspace_bytes, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    int32_t g[3];
+    if ((s = check_grid(dims, block, stride, g)) != NRR_OK) return s;
+    if (!(fraction > 0.0 && fraction <= 1.0))
+        return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
+    if (connectivity != 0 && connectivity != 6 && connectivity != 18 && connectivity != 26)
+        return fail(NRR_ERR_INVALID_ARG, "connectivity must be 0, 6, 18 or 26 (got %d)",
+                    connectivity);
+    if (!vol || !centers || !k_device || !workspace)
+        return fail(NRR_ERR_INVALID_ARG, "vol, centers, k_device and workspace must be non-NULL");
+    const int64_t n = (int64_t)g[0] * g[1] * g[2];
+    if (n > nrr::kSelectExCand)
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (limit %lld for the selection variants)",
+                    (long long)n, (long long)nrr::kSelectExCand);
+    const int64_t kmax = count_rule(n, fraction);
+    if (capacity < kmax)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "capacity %lld < %lld", (long long)capacity,
+                    (long long)kmax);
+    const nrr::SelectLayout L = nrr::select_layout(n);
+    if (workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
+                    L.total);
+    return hip_status(nrr::launch_select_ex(vol, dtype, dims, block, stride, g, fraction, mask,
+                                            connectivity, centers, k_device, workspace,
+                                            static_cast<hipStream_t>(stream)),
+                      "nrr_select_blocks_ex launch");
+}
+
 namespace {
 
 // Shared validation of the matching entry points; fills the stats layout.

@@ -26,6 +26,15 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
                          int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
                          void *workspace, hipStream_t stream);
 
+// Selection with a candidate mask and a connectivity pattern (0, 6, 18, 26)
+// for grids of at most kSelectExCand candidates; the number taken goes to
+// *k_device.  Uses the keys part of the selection workspace.
+constexpr int64_t kSelectExCand = 24576;
+hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            int32_t block, int32_t stride, const int32_t grid[3], double fraction,
+                            const uint8_t *mask, int32_t connectivity, int32_t *centers,
+                            int64_t *k_device, void *workspace, hipStream_t stream);
+
 // Batched selection (one workgroup per parameter set) for candidate grids of
 // at most kBatchCand blocks; `centers` points at the set's K output rows.
 constexpr int kBatchCand = 4096;

@@ -328,6 +328,206 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ ke
     }
 }
 
+
+// Inclusive scan of one value per thread over a 1024-thread workgroup
+// (wavefront shuffles, then the 16 wavefront totals); `tot` gets the sum.
+__device__ inline int64_t wg_scan1024_ex(int64_t v, int64_t *s_w, int64_t *tot) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) s_w[w] = v;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int i = 0; i < 16; ++i) {
+        const int64_t x = s_w[i];
+        before += i < w ? x : 0;
+        all += x;
+    }
+    __syncthreads();
+    *tot = all;
+    return v + before;
+}
+
+// ------------------------------------------------------- selection variants
+//
+// Selection with a candidate mask and a connectivity pattern (the region
+// restriction and the connectivity patterns of the parallel feature
+// selection paragraph): candidates whose centre lies outside the mask take
+// no part (N counts the others, K = floor(0.5 + N * F)); in rank order a
+// candidate is taken unless one of its 6/18/26 grid neighbours is already
+// taken, until K are taken.  That greedy visit equals the first K (in rank
+// order) of the whole greedy set, which parallel rounds compute: a block is
+// taken once every neighbour ranked above it has been left out, and left out
+// as soon as one of them is taken; each round settles at least the best
+// block still open, so the rounds end.  One 1024-thread workgroup, the
+// candidates' state and "ranked-above" neighbour masks in LDS.
+constexpr int kExCand = 24576;
+
+// Neighbour j (0..25) of the 26-neighbourhood, the centre skipped.
+__device__ inline void nb_offset(int j, int *dx, int *dy, int *dz) {
+    const int i = j < 13 ? j : j + 1;
+    *dx = i % 3 - 1;
+    *dy = (i / 3) % 3 - 1;
+    *dz = i / 9 - 1;
+}
+
+__device__ inline bool ranks_above(uint64_t ka, int64_t ia, uint64_t kb, int64_t ib) {
+    return ka > kb || (ka == kb && ia < ib);
+}
+
+__global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__ keys, int64_t n,
+                                                    int gx, int gy, int gz, int stride, int h,
+                                                    int nx, int ny,
+                                                    const uint8_t *__restrict__ mask,
+                                                    int connectivity, double fraction,
+                                                    int32_t *__restrict__ centers,
+                                                    int64_t *__restrict__ k_out) {
+    __shared__ uint8_t state[kExCand];       // 0 open, 1 taken, 2 left out, 3 outside the mask
+    __shared__ uint32_t above[kExCand];      // bit j: neighbour j ranks above
+    __shared__ uint32_t hist[2048];
+    __shared__ int64_t s_w[16];
+    __shared__ int s_changed;
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int64_t s_need;
+    const int tid = threadIdx.x;
+    // neighbours of the pattern: one, up to two, or up to three axis steps
+    const int max_steps = connectivity == 6 ? 1 : (connectivity == 18 ? 2 : (connectivity == 26 ? 3 : 0));
+    int64_t in_local = 0;
+    for (int64_t g = tid; g < n; g += 1024) {
+        const int ix = (int)(g % gx), iy = (int)((g / gx) % gy), iz = (int)(g / ((int64_t)gx * gy));
+        bool in = true;
+        if (mask)
+            in = mask[((int64_t)(iz * stride + h) * ny + (iy * stride + h)) * nx + (ix * stride + h)] != 0;
+        state[g] = in ? 0 : 3;
+        in_local += in;
+        uint32_t bits = 0;
+        const uint64_t kg = keys[g];
+        for (int j = 0; j < 26 && max_steps > 0; ++j) {
+            int dx, dy, dz;
+            nb_offset(j, &dx, &dy, &dz);
+            if ((dx != 0) + (dy != 0) + (dz != 0) > max_steps) continue;
+            const int x = ix + dx, y = iy + dy, z = iz + dz;
+            if (x < 0 || y < 0 || z < 0 || x >= gx || y >= gy || z >= gz) continue;
+            const int64_t q = ((int64_t)z * gy + y) * gx + x;
+            if (ranks_above(keys[q], q, kg, g)) bits |= 1u << j;
+        }
+        above[g] = bits;
+    }
+    int64_t n_in;
+    (void)wg_scan1024_ex(in_local, s_w, &n_in);
+    // the count rule over the candidates inside the mask
+    double kd = floor(0.5 + (double)n_in * fraction);
+    const int64_t k = kd < 0 ? 0 : (kd > (double)n_in ? n_in : (int64_t)kd);
+    __syncthreads();
+    // greedy set by rounds (every candidate inside the mask when no pattern)
+    for (;;) {
+        if (tid == 0) s_changed = 0;
+        __syncthreads();
+        int changed = 0;
+        for (int64_t g = tid; g < n; g += 1024) {
+            if (state[g] != 0) continue;
+            const int ix = (int)(g % gx), iy = (int)((g / gx) % gy), iz = (int)(g / ((int64_t)gx * gy));
+            bool any_taken = false, all_out = true;
+            uint32_t bits = above[g];
+            while (bits) {
+                const int j = __ffs(bits) - 1;
+                bits &= bits - 1;
+                int dx, dy, dz;
+                nb_offset(j, &dx, &dy, &dz);
+                const int64_t q = ((int64_t)(iz + dz) * gy + (iy + dy)) * gx + (ix + dx);
+                const uint8_t sq = state[q];
+                any_taken |= sq == 1;
+                all_out &= sq >= 2;
+            }
+            if (any_taken) {
+                state[g] = 2;
+                changed = 1;
+            } else if (all_out) {
+                state[g] = 1;
+                changed = 1;
+            }
+        }
+        if (changed) s_changed = 1;
+        __syncthreads();
+        if (!s_changed) break;
+        __syncthreads();
+    }
+    // the K best of the taken candidates: radix select of the K-th key among them
+    int64_t t_local = 0;
+    for (int64_t g = tid; g < n; g += 1024) t_local += state[g] == 1;
+    int64_t n_taken;
+    (void)wg_scan1024_ex(t_local, s_w, &n_taken);
+    const int64_t want = k < n_taken ? k : n_taken;
+    uint64_t kth = 0;
+    int64_t take_eq = 0;
+    const bool all = want == n_taken;  // keep every taken candidate
+    if (!all) {
+        if (tid == 0) {
+            s_prefix = 0;
+            s_mask = 0;
+            s_need = want;
+        }
+        __syncthreads();
+        for (int hi = 63; hi >= 0; hi -= 11) {
+            const int shift = hi - 10 > 0 ? hi - 10 : 0, width = hi - shift + 1;
+            const uint64_t dmask = (width == 64 ? ~0ull : ((1ull << width) - 1)) << shift;
+            for (int i = tid; i < 2048; i += 1024) hist[i] = 0;
+            __syncthreads();
+            const uint64_t prefix = s_prefix, pm = s_mask;
+            for (int64_t g = tid; g < n; g += 1024) {
+                const uint64_t kv = keys[g];
+                if (state[g] == 1 && (kv & pm) == prefix) atomicAdd(&hist[(kv & dmask) >> shift], 1u);
+            }
+            __syncthreads();
+            const uint32_t a = hist[2047 - 2 * tid], b = hist[2046 - 2 * tid];
+            int64_t tot;
+            const int64_t incl = wg_scan1024_ex((int64_t)a + b, s_w, &tot);
+            const int64_t above_cnt = incl - a - b, need = s_need;
+            __syncthreads();
+            if (above_cnt < need && need <= incl) {
+                const bool first = above_cnt + a >= need;
+                const uint64_t d = (uint64_t)(first ? 2047 - 2 * tid : 2046 - 2 * tid);
+                s_need = need - (first ? above_cnt : above_cnt + a);
+                s_prefix = prefix | (d << shift);
+                s_mask = pm | dmask;
+            }
+            __syncthreads();
+        }
+        kth = s_prefix;
+        take_eq = s_need;
+    }
+    // ordered compaction: thread t owns candidates [t*per, (t+1)*per)
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = (int64_t)tid * per < n ? (int64_t)tid * per : n, hi = lo + per < n ? lo + per : n;
+    int64_t lg = 0, le = 0;
+    for (int64_t g = lo; g < hi; ++g) {
+        if (state[g] != 1) continue;
+        const uint64_t kv = keys[g];
+        lg += all || kv > kth;
+        le += !all && kv == kth;
+    }
+    int64_t tg, te;
+    int64_t gt_before = wg_scan1024_ex(lg, s_w, &tg) - lg;
+    int64_t eq_before = wg_scan1024_ex(le, s_w, &te) - le;
+    for (int64_t g = lo; g < hi; ++g) {
+        if (state[g] != 1) continue;
+        const uint64_t kv = keys[g];
+        const bool is_gt = all || kv > kth, is_eq = !all && kv == kth;
+        if (is_gt || (is_eq && eq_before < take_eq)) {
+            const int64_t pos = gt_before + (eq_before < take_eq ? eq_before : take_eq);
+            const int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+            centers[3 * pos + 0] = (int32_t)(ix * stride + h);
+            centers[3 * pos + 1] = (int32_t)(iy * stride + h);
+            centers[3 * pos + 2] = (int32_t)(iz * stride + h);
+        }
+        gt_before += is_gt;
+        eq_before += is_eq;
+    }
+    if (tid == 0) *k_out = want;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Batched selection for small candidate grids.  The keys of every set's
@@ -460,6 +660,27 @@ hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t d
                            dim3(256), 0, stream, vol, dtype == NRR_U16 ? 1 : 0, dims[0], dims[1],
                            sets);
     hipLaunchKernelGGL(k_select_batch, dim3((unsigned)nsets), dim3(1024), 0, stream, sets);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            int32_t block, int32_t stride, const int32_t grid[3], double fraction,
+                            const uint8_t *mask, int32_t connectivity, int32_t *centers,
+                            int64_t *k_device, void *workspace, hipStream_t stream) {
+    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    SelectLayout L = select_layout(n);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + L.keys_off);
+    if (dtype == NRR_U16)
+        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(vol), dims[0], dims[1], block, stride,
+                           grid[0], grid[1], n, keys);
+    else
+        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           stream, static_cast<const float *>(vol), dims[0], dims[1], block,
+                           stride, grid[0], grid[1], n, keys);
+    hipLaunchKernelGGL(k_select_ex, dim3(1), dim3(1024), 0, stream, keys, n, grid[0], grid[1],
+                       grid[2], stride, (block - 1) / 2, dims[0], dims[1], mask, connectivity,
+                       fraction, centers, k_device);
     return hipGetLastError();
 }
 

@@ -190,3 +190,21 @@ def test_request_footprint_closed_form(lib):
     assert fp == want
     with pytest.raises(nrr.NrrError):
         nrr.request_footprint(ref, flt, 6, 7, 5, 0.25)
+
+
+def test_select_ex_validation(lib):
+    import ctypes
+
+    buf = (ctypes.c_byte * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    dims = (ctypes.c_int32 * 3)(64, 64, 64)
+    f = lib.nrr_select_blocks_ex
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                  ctypes.c_double, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                  ctypes.c_void_p]
+    assert f(p, 0, dims, 7, 7, 0.2, None, 5, p, 1000, p, p, 1 << 30, None) == 1  # bad pattern
+    assert f(p, 0, dims, 7, 7, 1.5, None, 6, p, 1000, p, p, 1 << 30, None) == 1  # bad fraction
+    assert f(p, 0, dims, 3, 1, 0.2, None, 6, p, 10 ** 6, p, p, 1 << 30, None) == 4  # 62^3 cands
+    assert f(p, 0, dims, 7, 7, 0.2, None, 6, p, 1, p, p, 1 << 30, None) == 2  # capacity

@@ -1,0 +1,87 @@
+"""GPU: selection with a candidate mask and a connectivity pattern, against
+the oracle (bit-exact: same centres, same order)."""
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_10868_amd as nrr
+from paper_2308_10868_amd import synth
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nrr.load()
+    return torch
+
+
+def gpu_ex(vol, b, s, f, mask, conn):
+    import torch
+
+    c = nrr.select_blocks_ex(to_dev(vol), b, s, f, None if mask is None else to_dev(mask), conn)
+    torch.cuda.synchronize()
+    return to_host(c)
+
+
+@pytest.mark.parametrize("conn", [0, 6, 18, 26])
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_tiny_random_with_masks(torch_dev, conn, dtype):
+    for seed in range(3):
+        p = synth.gen_random(30 + seed, (19, 15, 13), dtype, smooth=1.0)
+        rng = np.random.default_rng(seed)
+        mask = (rng.random(p.ref.shape) < 0.7).astype(np.uint8) if seed != 0 else None
+        for b, s, f in [(3, 2, 0.4), (3, 1, 0.2), (5, 3, 0.9), (3, 3, 1.0)]:
+            say("select_ex", dtype, conn, seed, b, s, f)
+            want, _ = oracle.select_ex(p.ref, b, s, f, mask, conn)
+            got = gpu_ex(p.ref, b, s, f, mask, conn)
+            assert np.array_equal(got, want), (dtype, conn, seed, b, s, f)
+
+
+def test_golden_cases(torch_dev):
+    from tests.test_oracle_select_ex import golden_volume
+
+    for case in json.load(open(os.path.join(HERE, "golden", "select_connectivity.json")))["cases"]:
+        vol, mask = golden_volume(case)
+        got = gpu_ex(vol, 3, 3, case["fraction"], mask, case["connectivity"])
+        gx = case["dims"][0] // 3
+        want = np.array([[3 * (g % gx) + 1, 3 * (g // gx) + 1, 1] for g in case["taken"]],
+                        dtype=np.int32).reshape(-1, 3)
+        assert np.array_equal(got, want), case["why"]
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_mri_workload_with_region_mask(torch_dev, conn):
+    p = synth.gen_mri_u16(seed=0)
+    nz, ny, nx = p.ref.shape
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    # an ellipsoidal region (a stand-in for the intracranial cavity)
+    mask = (((x - nx / 2) / (0.42 * nx)) ** 2 + ((y - ny / 2) / (0.45 * ny)) ** 2 +
+            ((z - nz / 2) / (0.48 * nz)) ** 2 <= 1.0).astype(np.uint8)
+    say("select_ex mri", conn)
+    want, _ = oracle.select_ex(p.ref, 7, 7, 0.25, mask, conn)
+    got = gpu_ex(p.ref, 7, 7, 0.25, mask, conn)
+    assert len(want) > 300  # a nontrivial set (26-connectivity leaves about 800)
+    assert np.array_equal(got, want)
+
+
+def test_plain_special_case_equals_select_blocks(torch_dev):
+    p = synth.gen_translation_f32(seed=0)
+    a = to_host(nrr.select_blocks(to_dev(p.ref), 7, 7, 0.2))
+    b = gpu_ex(p.ref, 7, 7, 0.2, None, 0)
+    assert np.array_equal(a, b)
