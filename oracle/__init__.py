@@ -48,6 +48,8 @@ def _load():
         i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         lib.oracle_select.restype = i64
         lib.oracle_select.argtypes = [P, ctypes.c_int, P, i32, i32, f64, P, P, i64]
+        lib.oracle_structure_confidence.restype = ctypes.c_int
+        lib.oracle_structure_confidence.argtypes = [P, ctypes.c_int, P, P, i64, i32, P, P]
         lib.oracle_select_ex.restype = i64
         lib.oracle_select_ex.argtypes = [P, ctypes.c_int, P, i32, i32, f64, P, i32, P, P, i64]
         lib.oracle_block_variance.restype = ctypes.c_int
@@ -149,6 +151,19 @@ def select_ex(vol: np.ndarray, block: int, stride: int, fraction: float, mask=No
     if k < 0:
         raise ValueError("oracle_select_ex rejected the arguments (%d)" % k)
     return out[:k].copy(), var[:k].copy()
+
+
+def structure_confidence(ref: np.ndarray, centers: np.ndarray, block: int, conf: np.ndarray):
+    """Directional confidence S per block: f64 [n, 6] = (xx, yy, zz, xy, xz, yz)."""
+    ref, dt = _vol(ref)
+    c = np.ascontiguousarray(centers, dtype=np.int32).reshape(-1, 3)
+    n = c.shape[0]
+    cf = np.ascontiguousarray(conf, dtype=np.float64).reshape(n)
+    out = np.zeros((max(n, 1), 6), dtype=np.float64)
+    if _load().oracle_structure_confidence(_ptr(ref), dt, _ptr(_dims(ref)), _ptr(c), n, block,
+                                           _ptr(cf), _ptr(out)):
+        raise ValueError("oracle_structure_confidence rejected the arguments")
+    return out[:n]
 
 
 def match(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block: int, window: int):

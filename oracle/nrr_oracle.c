@@ -443,6 +443,69 @@ int oracle_valid_shifts(const int32_t dims[3], const int32_t *centers, int64_t n
     return 0;
 }
 
+/*
+ * Directional confidence (the confidence matrix S of the FEM update equation,
+ * for which the paper gives no formula): per block centred at c, the
+ * structure tensor J = sum over the block's voxels p of g(p) g(p)^T, with
+ * g the intensity gradient of `ref` by central differences,
+ * g_x(p) = (ref(p+e_x) - ref(p-e_x)) / 2, and one-sided differences
+ * ref(p+e_x) - ref(p) / ref(p) - ref(p-e_x) on the volume's first / last
+ * plane of that axis.  S = conf * J / trace(J) (S = 0 when trace(J) = 0).
+ * out[6k..6k+5] = S_xx, S_yy, S_zz, S_xy, S_xz, S_yz.  A block not inside
+ * the volume gets S = 0.  FP64.
+ */
+static double grad_axis(const void *vol, int dtype, const int32_t dims[3], int64_t x, int64_t y,
+                        int64_t z, int axis) {
+    int64_t p[3] = {x, y, z};
+    const int64_t n = dims[axis];
+    int64_t lo[3] = {x, y, z}, hi[3] = {x, y, z};
+    double scale = 0.5;
+    if (p[axis] == 0) {
+        hi[axis] = 1;
+        scale = 1.0;
+    } else if (p[axis] == n - 1) {
+        lo[axis] = n - 2;
+        scale = 1.0;
+    } else {
+        lo[axis] = p[axis] - 1;
+        hi[axis] = p[axis] + 1;
+    }
+    if (n == 1) return 0.0;
+    return scale * (voxel(vol, dtype, dims, hi[0], hi[1], hi[2]) -
+                    voxel(vol, dtype, dims, lo[0], lo[1], lo[2]));
+}
+
+int oracle_structure_confidence(const void *ref, int dtype, const int32_t dims[3],
+                                const int32_t *centers, int64_t n, int32_t b, const double *conf,
+                                double *out) {
+    if (b < 1 || (b % 2) == 0) return -1;
+    const int32_t h = (b - 1) / 2;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t cx = centers[3 * k], cy = centers[3 * k + 1], cz = centers[3 * k + 2];
+        double j[6] = {0, 0, 0, 0, 0, 0};
+        if (cx - h >= 0 && cy - h >= 0 && cz - h >= 0 && cx + h < dims[0] && cy + h < dims[1] &&
+            cz + h < dims[2]) {
+            for (int64_t z = cz - h; z <= cz + h; ++z)
+                for (int64_t y = cy - h; y <= cy + h; ++y)
+                    for (int64_t x = cx - h; x <= cx + h; ++x) {
+                        const double gx = grad_axis(ref, dtype, dims, x, y, z, 0);
+                        const double gy = grad_axis(ref, dtype, dims, x, y, z, 1);
+                        const double gz = grad_axis(ref, dtype, dims, x, y, z, 2);
+                        j[0] += gx * gx;
+                        j[1] += gy * gy;
+                        j[2] += gz * gz;
+                        j[3] += gx * gy;
+                        j[4] += gx * gz;
+                        j[5] += gy * gz;
+                    }
+        }
+        const double tr = j[0] + j[1] + j[2];
+        for (int e = 0; e < 6; ++e) out[6 * k + e] = tr > 0.0 ? conf[k] * j[e] / tr : 0.0;
+    }
+    return 0;
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

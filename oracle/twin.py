@@ -140,3 +140,23 @@ def match(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block: int, win
         ncc[k] = best
         conf[k] = max(0.0, best)
     return disp, ncc, conf
+
+
+def structure_confidence(ref: np.ndarray, centers, block: int, conf) -> np.ndarray:
+    """Directional confidence by numpy.gradient (central differences inside,
+    one-sided first differences on the border planes)."""
+    v = ref.astype(np.float64)
+    gz, gy, gx = np.gradient(v, edge_order=1)
+    h = (block - 1) // 2
+    out = np.zeros((len(centers), 6))
+    nz, ny, nx = v.shape
+    for k, (cx, cy, cz) in enumerate(np.asarray(centers).reshape(-1, 3)):
+        if not (cx - h >= 0 and cy - h >= 0 and cz - h >= 0 and cx + h < nx and cy + h < ny
+                and cz + h < nz):
+            continue
+        sl = (slice(cz - h, cz + h + 1), slice(cy - h, cy + h + 1), slice(cx - h, cx + h + 1))
+        a, b, c = gx[sl].ravel(), gy[sl].ravel(), gz[sl].ravel()
+        j = np.array([a @ a, b @ b, c @ c, a @ b, a @ c, b @ c])
+        tr = j[:3].sum()
+        out[k] = conf[k] * j / tr if tr > 0 else 0.0
+    return out

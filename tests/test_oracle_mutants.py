@@ -47,9 +47,19 @@ MUTANTS_EX = {
     "faces_skip_z": ("for (int dz = -1; dz <= 1 && !blocked && connectivity; ++dz)",
                      "for (int dz = 0; dz <= 0 && !blocked && connectivity; ++dz)"),
 }
+# mistakes in the directional confidence
+MUTANTS_CONF = {
+    "border_difference_halved": ("    if (p[axis] == 0) {\n        hi[axis] = 1;\n        scale = 1.0;",
+                                 "    if (p[axis] == 0) {\n        hi[axis] = 1;\n        scale = 0.5;"),
+    "cross_term_sign": ("j[5] += gy * gz;", "j[5] -= gy * gz;"),
+    "not_trace_normalised": ("out[6 * k + e] = tr > 0.0 ? conf[k] * j[e] / tr : 0.0;",
+                             "out[6 * k + e] = tr > 0.0 ? conf[k] * j[e] : 0.0;"),
+}
 PIN_FILES = {name: "test_oracle_pins.py" for name in MUTANTS}
+PIN_FILES.update({name: "test_oracle_confidence.py" for name in MUTANTS_CONF})
 PIN_FILES.update({name: "test_oracle_select_ex.py" for name in MUTANTS_EX})
 MUTANTS.update(MUTANTS_EX)
+MUTANTS.update(MUTANTS_CONF)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
