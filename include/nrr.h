@@ -185,6 +185,24 @@ nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype 
                                     float *conf, const void *workspace, size_t workspace_bytes,
                                     void *stream);
 
+/* Directional confidence for the biomechanical solve.  The FEM update
+ * equation weights each block's displacement by a confidence matrix S; the
+ * paper gives no formula for it.  This returns, per block centred at
+ * centers[k] (block edge `block`), S = conf[k] * J / trace(J) with J the
+ * structure tensor of `ref` over the block: the sum over its voxels of
+ * g g^T, g the intensity gradient by central differences (one-sided first
+ * differences on the volume's border planes).  S = 0 when trace(J) = 0 or
+ * the block is not inside the volume.
+ *
+ *  ref      device volume of dtype; centers device int32 [n][3];
+ *  conf     device float [n] (e.g. nrr_block_match's conf);
+ *  out      device float [n][6] = S_xx, S_yy, S_zz, S_xy, S_xz, S_yz.
+ * Errors: INVALID_ARG (bad block, null pointers with n > 0), HIP.  n == 0 is
+ * a no-op. */
+nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int32_t dims[3],
+                                    const int32_t *centers, int64_t n, int32_t block,
+                                    const float *conf, float *out, void *stream);
+
 /* ------------------------------------------------------------------ tuning
  * Tile-shape autotuner.  The exhaustive search can run with several compiled
  * shapes (displacement tile per thread, threads per workgroup, prefetch of

@@ -32,6 +32,7 @@ __all__ = [
     "select_blocks_ex",
     "block_match",
     "window_stats",
+    "structure_confidence",
     "tune_match",
     "tuned_shape",
     "clear_tuning",
@@ -128,6 +129,7 @@ def load():
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
+        "nrr_structure_confidence": (st, [P, ctypes.c_int, P, P, I64, I32, P, P, P]),
         "nrr_tune_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, I32, P, P,
                                 P]),
         "nrr_tuned_shape": (st, [ctypes.c_int, I32, I32, P]),
@@ -320,6 +322,24 @@ def block_match(ref, flt, centers, block: int, window: int, workspace=None, out=
                                ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
     return disp, ncc, conf
+
+
+def structure_confidence(ref, centers, block: int, conf):
+    """Directional confidence S per block (float32 [n, 6]: xx, yy, zz, xy, xz,
+    yz) = conf * structure tensor / its trace (see include/nrr.h)."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    n = centers.shape[0]
+    out = torch.zeros((max(n, 1), 6), dtype=torch.float32, device=ref.device)
+    if n == 0:
+        return out[:0]
+    conf = conf.contiguous().to(torch.float32)
+    _check(lib.nrr_structure_confidence(ctypes.c_void_p(ref.data_ptr()), dt, _dims3(dims),
+                                        ctypes.c_void_p(centers.data_ptr()), n, block,
+                                        ctypes.c_void_p(conf.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(ref)))
+    return out[:n]
 
 
 # ------------------------------------------------------------------ tuning

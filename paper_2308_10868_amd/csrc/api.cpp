@@ -381,6 +381,22 @@ nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
                      L, st);
 }
 
+nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int32_t dims[3],
+                                    const int32_t *centers, int64_t n, int32_t block,
+                                    const float *conf, float *out, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    int32_t g[3];
+    if ((s = check_grid(dims, block, 1, g)) != NRR_OK) return s;
+    if (n < 0) return fail(NRR_ERR_INVALID_ARG, "n must be >= 0");
+    if (n == 0) return ok();
+    if (!ref || !centers || !conf || !out)
+        return fail(NRR_ERR_INVALID_ARG, "ref, centers, conf and out must be non-NULL");
+    return hip_status(nrr::launch_structure_conf(ref, dtype, dims, centers, n, block, conf, out,
+                                                 static_cast<hipStream_t>(stream)),
+                      "structure confidence launch");
+}
+
 // ------------------------------------------------------------------ tuning
 
 nrr_status nrr_tune_match(const void *ref, const void *flt, nrr_dtype dtype,

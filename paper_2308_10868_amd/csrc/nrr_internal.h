@@ -79,6 +79,11 @@ StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
 hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3], int32_t block,
                         void *workspace, hipStream_t stream);
 
+// Directional confidence per block: out[n][6] = conf * J / trace(J).
+hipError_t launch_structure_conf(const void *ref, nrr_dtype dtype, const int32_t dims[3],
+                                 const int32_t *centers, int64_t n, int32_t block,
+                                 const float *conf, float *out, hipStream_t stream);
+
 // -------------------------------------------------------------- matching
 struct MatchArgs {
     const void *ref;

@@ -210,9 +210,82 @@ __global__ __launch_bounds__(256) void k_pair_volume(const uint16_t *__restrict_
     }
 }
 
+// Directional confidence (the FEM update's confidence matrix S, no formula in
+// the paper): S = conf * J / trace(J) with J the block's intensity structure
+// tensor, sum over its voxels of g g^T, g by central differences of `ref`
+// (one-sided on the volume's border planes).  One wavefront per block, FP64
+// sums (exact for 12-bit data), S as (xx, yy, zz, xy, xz, yz).
+template <typename Vox>
+__global__ __launch_bounds__(256) void k_structure_conf(const Vox *__restrict__ ref, int nx, int ny,
+                                                        int nz, const int32_t *__restrict__ centers,
+                                                        int64_t n, int b,
+                                                        const float *__restrict__ conf,
+                                                        float *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= n) return;  // whole wavefront leaves together
+    const int h = (b - 1) / 2;
+    const int cx = centers[3 * k], cy = centers[3 * k + 1], cz = centers[3 * k + 2];
+    const bool inside = cx - h >= 0 && cy - h >= 0 && cz - h >= 0 && cx + h < nx && cy + h < ny &&
+                        cz + h < nz;
+    double j[6] = {0, 0, 0, 0, 0, 0};
+    if (inside) {
+        const int64_t sy = nx, sz = (int64_t)nx * ny;
+        auto at = [&](int x, int y, int z) {
+            return (double)ref[(int64_t)z * sz + (int64_t)y * sy + x];
+        };
+        auto diff = [&](int x, int y, int z, int dx, int dy, int dz, int p, int len) {
+            if (len == 1) return 0.0;
+            if (p == 0) return at(x + dx, y + dy, z + dz) - at(x, y, z);
+            if (p == len - 1) return at(x, y, z) - at(x - dx, y - dy, z - dz);
+            return 0.5 * (at(x + dx, y + dy, z + dz) - at(x - dx, y - dy, z - dz));
+        };
+        const int nb = b * b * b;
+        for (int o = lane; o < nb; o += 64) {
+            const int x = cx - h + o % b, y = cy - h + (o / b) % b, z = cz - h + o / (b * b);
+            const double gx = diff(x, y, z, 1, 0, 0, x, nx);
+            const double gy = diff(x, y, z, 0, 1, 0, y, ny);
+            const double gz = diff(x, y, z, 0, 0, 1, z, nz);
+            j[0] += gx * gx;
+            j[1] += gy * gy;
+            j[2] += gz * gz;
+            j[3] += gx * gy;
+            j[4] += gx * gz;
+            j[5] += gy * gz;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e)
+        for (int off = 32; off > 0; off >>= 1) j[e] += __shfl_xor(j[e], off);
+    if (lane < 6) {
+        const double tr = j[0] + j[1] + j[2];
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+            if (e == lane) v = j[e];
+        out[6 * k + lane] = tr > 0.0 ? (float)((double)conf[k] * v / tr) : 0.0f;
+    }
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
+
+hipError_t launch_structure_conf(const void *ref, nrr_dtype dtype, const int32_t dims[3],
+                                 const int32_t *centers, int64_t n, int32_t block,
+                                 const float *conf, float *out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + 3) / 4));
+    if (dtype == NRR_U16)
+        hipLaunchKernelGGL(k_structure_conf<uint16_t>, grid, dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(ref), dims[0], dims[1], dims[2], centers,
+                           n, block, conf, out);
+    else
+        hipLaunchKernelGGL(k_structure_conf<float>, grid, dim3(256), 0, stream,
+                           static_cast<const float *>(ref), dims[0], dims[1], dims[2], centers, n,
+                           block, conf, out);
+    return hipGetLastError();
+}
 
 StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block) {
     StatsLayout L;

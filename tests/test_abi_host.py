@@ -208,3 +208,20 @@ def test_select_ex_validation(lib):
     assert f(p, 0, dims, 7, 7, 1.5, None, 6, p, 1000, p, p, 1 << 30, None) == 1  # bad fraction
     assert f(p, 0, dims, 3, 1, 0.2, None, 6, p, 10 ** 6, p, p, 1 << 30, None) == 4  # 62^3 cands
     assert f(p, 0, dims, 7, 7, 0.2, None, 6, p, 1, p, p, 1 << 30, None) == 2  # capacity
+
+
+def test_structure_confidence_validation(lib):
+    import ctypes
+
+    buf = (ctypes.c_byte * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    dims = (ctypes.c_int32 * 3)(32, 32, 32)
+    f = lib.nrr_structure_confidence
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert f(p, 0, dims, p, 4, 6, p, p, None) == 1      # even block
+    assert f(p, 7, dims, p, 4, 7, p, p, None) == 1      # unknown dtype
+    assert f(p, 0, dims, p, -1, 7, p, p, None) == 1     # negative count
+    assert f(p, 0, dims, None, 4, 7, p, p, None) == 1   # null centres
+    assert f(None, 0, dims, None, 0, 7, None, None, None) == 0  # n == 0: no-op

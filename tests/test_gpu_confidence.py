@@ -1,0 +1,114 @@
+"""GPU: directional confidence S = conf * J / trace(J) per block, against the
+oracle (FP64 sums on both sides, float32 output: relative 1e-6)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_10868_amd as nrr
+from paper_2308_10868_amd import synth
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nrr.load()
+    return torch
+
+
+def gpu_conf(ref, centers, b, conf):
+    import torch
+
+    c = torch.from_numpy(np.ascontiguousarray(centers, dtype=np.int32)).cuda()
+    cf = torch.from_numpy(np.ascontiguousarray(conf, dtype=np.float32)).cuda()
+    out = nrr.structure_confidence(to_dev(ref), c, b, cf)
+    torch.cuda.synchronize()
+    return to_host(out)
+
+
+def check(got, want, conf):
+    assert got.shape == want.shape
+    scale = np.maximum(np.abs(np.asarray(conf, dtype=np.float64)), 1e-30)[:, None]
+    err = np.abs(got.astype(np.float64) - want) / scale
+    assert err.max(initial=0.0) < 1e-6, err.max()
+
+
+def border_centres(dims, b, rng, n):
+    """Centres spread over the volume with many blocks touching a face, some
+    outside the volume (half-block over an edge)."""
+    h = (b - 1) // 2
+    nx, ny, nz = dims
+    c = np.stack([rng.integers(h, nx - h, n), rng.integers(h, ny - h, n),
+                  rng.integers(h, nz - h, n)], axis=1)
+    c[: n // 4, 0] = h                 # touching x = 0
+    c[n // 4: n // 2, 2] = nz - 1 - h  # touching the last plane
+    c[-3:, 1] = ny - h                 # one past the top: outside
+    return c.astype(np.int32)
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+@pytest.mark.parametrize("b", [3, 7, 13])
+def test_random_volumes(torch_dev, dtype, b):
+    for seed in range(2):
+        p = synth.gen_random(50 + seed, (23, 19, 17), dtype, smooth=1.0)
+        rng = np.random.default_rng(seed)
+        dims = (p.ref.shape[2], p.ref.shape[1], p.ref.shape[0])
+        cen = border_centres(dims, b, rng, 40)
+        conf = rng.random(len(cen))
+        conf[5] = 0.0
+        say("confidence", dtype, b, seed)
+        want = oracle.structure_confidence(p.ref, cen, b, conf.astype(np.float32))
+        got = gpu_conf(p.ref, cen, b, conf)
+        check(got, want, conf)
+        assert np.all(got[-3:] == 0.0)
+
+
+def test_flat_and_empty(torch_dev):
+    vol = np.full((9, 11, 13), 1234, dtype=np.uint16)
+    cen = np.array([[5, 5, 4], [6, 4, 4]], dtype=np.int32)
+    say("confidence flat")
+    got = gpu_conf(vol, cen, 5, np.ones(2))
+    assert np.all(got == 0.0)
+    got = gpu_conf(vol, np.zeros((0, 3), np.int32), 5, np.zeros(0))
+    assert got.shape == (0, 6)
+
+
+def test_after_match_mri(torch_dev):
+    """On the MRI pair at a reduced size, S from the search's own conf."""
+    import torch
+
+    p = synth.gen_mri_u16(seed=3, dims=(96, 80, 48))
+    ref, flt = to_dev(p.ref), to_dev(p.flt)
+    b, w = 7, 4
+    centers = nrr.select_blocks(ref, b, 7, 0.5)
+    disp, ncc, conf = nrr.block_match(ref, flt, centers, b, w)
+    torch.cuda.synchronize()
+    say("confidence mri", centers.shape[0])
+    got = to_host(nrr.structure_confidence(ref, centers, b, conf))
+    torch.cuda.synchronize()
+    want = oracle.structure_confidence(p.ref, to_host(centers), b, to_host(conf))
+    check(got, want, to_host(conf))
+    tr = got[:, 0] + got[:, 1] + got[:, 2]
+    assert np.allclose(tr, to_host(conf), rtol=1e-5, atol=1e-6)
+
+
+def test_invalid_arguments(torch_dev):
+    import torch
+
+    ref = to_dev(np.zeros((9, 9, 9), dtype=np.float32))
+    c = torch.zeros((1, 3), dtype=torch.int32, device="cuda")
+    cf = torch.zeros(1, dtype=torch.float32, device="cuda")
+    with pytest.raises(nrr.NrrError):
+        nrr.structure_confidence(ref, c, 4, cf)
