@@ -112,3 +112,25 @@ def test_invalid_arguments(torch_dev):
     cf = torch.zeros(1, dtype=torch.float32, device="cuda")
     with pytest.raises(nrr.NrrError):
         nrr.structure_confidence(ref, c, 4, cf)
+
+
+def test_fem_loop_recovers_shift(torch_dev):
+    """Selection, search and directional confidence on the GPU feed the CPU
+    biomechanical update, which carries the mesh to the volume's shift."""
+    from paper_2308_10868_amd import fem
+
+    shift = (2, -1, 1)
+    ref = synth.gen_random(7, (32, 32, 32), "f32", smooth=1.0).ref
+    flt = np.roll(ref, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    mask = np.zeros(ref.shape, np.uint8)
+    mask[5:27, 5:27, 5:27] = 1
+    r, f = to_dev(ref), to_dev(flt)
+    say("fem loop")
+    centers = nrr.select_blocks_ex(r, 5, 3, 0.5, to_dev(mask), 6)
+    disp, ncc, conf = nrr.block_match(r, f, centers, 5, 3)
+    s = nrr.structure_confidence(r, centers, 5, conf)
+    torch_dev.cuda.synchronize()
+    assert np.all(to_host(disp) == shift)
+    mesh, u, _ = fem.register((32, 32, 32), to_host(centers), to_host(disp), to_host(s),
+                              spacing=8.0, iterations=3)
+    assert np.abs(u - np.array(shift, dtype=np.float64)).max() < 1e-6
