@@ -64,6 +64,10 @@ def _load():
         lib.oracle_select_count.argtypes = [i64, f64]
         lib.oracle_grid_shape.restype = ctypes.c_int
         lib.oracle_grid_shape.argtypes = [P, i32, i32, P]
+        lib.oracle_select_aniso.restype = i64
+        lib.oracle_select_aniso.argtypes = [P, ctypes.c_int, P, P, P, f64, P, P, i64]
+        lib.oracle_match_aniso.restype = ctypes.c_int
+        lib.oracle_match_aniso.argtypes = [P, P, ctypes.c_int, P, P, i64, P, P, P, P, P]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -179,6 +183,48 @@ def match(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block: int, win
     if _load().oracle_match(_ptr(ref), _ptr(flt), dt, _ptr(_dims(ref)), _ptr(c), n, block, window,
                             _ptr(disp), _ptr(ncc), _ptr(conf)):
         raise ValueError("oracle_match rejected the arguments")
+    return disp[:n], ncc[:n], conf[:n]
+
+
+def _triple(v) -> np.ndarray:
+    t = np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.int32), (3,)))
+    return t
+
+
+def select_aniso(vol: np.ndarray, block, stride, fraction: float):
+    """Selection with per-axis block edges and strides ((x, y, z) triples):
+    centres int32[K, 3] in ascending grid index and their FP64 variances."""
+    vol, dt = _vol(vol)
+    dims = _dims(vol)
+    b, s = _triple(block), _triple(stride)
+    if np.any(b < 1) or np.any(b % 2 == 0) or np.any(s < 1) or np.any(dims < b):
+        raise ValueError("bad per-axis block/stride")
+    n = int(np.prod((dims - b) // s + 1))
+    cap = max(select_count(n, fraction), 1)
+    centers = np.zeros((cap, 3), dtype=np.int32)
+    var = np.zeros(cap, dtype=np.float64)
+    k = _load().oracle_select_aniso(_ptr(vol), dt, _ptr(dims), _ptr(b), _ptr(s), fraction,
+                                    _ptr(centers), _ptr(var), cap)
+    if k < 0:
+        raise ValueError("oracle_select_aniso rejected the arguments (%d)" % k)
+    return centers[:k], var[:k]
+
+
+def match_aniso(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block, window):
+    """Exhaustive NCC search with per-axis block edges and half windows:
+    (disp int32[n,3], ncc f64[n], conf f64[n])."""
+    ref, dt = _vol(ref)
+    flt, dt2 = _vol(flt)
+    assert dt == dt2 and ref.shape == flt.shape
+    c = np.ascontiguousarray(centers, dtype=np.int32).reshape(-1, 3)
+    n = c.shape[0]
+    disp = np.zeros((max(n, 1), 3), dtype=np.int32)
+    ncc = np.zeros(max(n, 1), dtype=np.float64)
+    conf = np.zeros(max(n, 1), dtype=np.float64)
+    if _load().oracle_match_aniso(_ptr(ref), _ptr(flt), dt, _ptr(_dims(ref)), _ptr(c), n,
+                                  _ptr(_triple(block)), _ptr(_triple(window)), _ptr(disp),
+                                  _ptr(ncc), _ptr(conf)):
+        raise ValueError("oracle_match_aniso rejected the arguments")
     return disp[:n], ncc[:n], conf[:n]
 
 

@@ -506,6 +506,169 @@ int oracle_structure_confidence(const void *ref, int dtype, const int32_t dims[3
     return 0;
 }
 
+/*
+ * Per-axis block and window sizes.  The paper's parameter list gives the
+ * half block size and the half search window per anatomical axis (the
+ * "Deep Learning Model Architecture" section), so a block need not be a
+ * cube.  Here b[a] = 2*Bs[a] + 1 and w[a] = Ws[a] for a = x, y, z; the
+ * candidate grid takes its own stride per axis.  Everything else follows
+ * the cubic readings: the grid, the count rule, ranking and ties, the
+ * displacement set and shift index, NCC, argmax and the flat and outside
+ * rules, with b^3 replaced by bx*by*bz and (2W+1) per axis by (2w[a]+1).
+ */
+
+/* Sum and sum of squares of the bx*by*bz block with lowest corner (x0,y0,z0)
+   in z, y, x order; the exact integer key for 12-bit data. */
+static void aniso_block_variance(const void *vol, int dtype, const int32_t dims[3],
+                                 const int32_t b[3], int64_t x0, int64_t y0, int64_t z0,
+                                 double *key, double *var) {
+    const double nb = (double)b[0] * b[1] * b[2];
+    double sum = 0.0;
+    int64_t isum = 0, isq = 0;
+    for (int64_t z = z0; z < z0 + b[2]; ++z)
+        for (int64_t y = y0; y < y0 + b[1]; ++y)
+            for (int64_t x = x0; x < x0 + b[0]; ++x) {
+                const double v = voxel(vol, dtype, dims, x, y, z);
+                sum += v;
+                if (dtype == ORACLE_U16) {
+                    isum += (int64_t)v;
+                    isq += (int64_t)v * (int64_t)v;
+                }
+            }
+    const double mean = sum / nb;
+    double ss = 0.0;
+    for (int64_t z = z0; z < z0 + b[2]; ++z)
+        for (int64_t y = y0; y < y0 + b[1]; ++y)
+            for (int64_t x = x0; x < x0 + b[0]; ++x) {
+                const double d = voxel(vol, dtype, dims, x, y, z) - mean;
+                ss += d * d;
+            }
+    *var = ss / nb;
+    if (dtype == ORACLE_U16)
+        *key = (double)((int64_t)b[0] * b[1] * b[2] * isq - isum * isum);
+    else
+        *key = *var;
+}
+
+static int aniso_sizes_ok(const int32_t dims[3], const int32_t b[3], const int32_t s[3],
+                          int32_t grid[3]) {
+    for (int a = 0; a < 3; ++a) {
+        if (b[a] < 1 || (b[a] % 2) == 0 || s[a] < 1 || dims[a] < b[a]) return 0;
+        grid[a] = (dims[a] - b[a]) / s[a] + 1;
+    }
+    return 1;
+}
+
+/* Selection with per-axis block edges b[3] and strides stride[3]. */
+int64_t oracle_select_aniso(const void *vol, int dtype, const int32_t dims[3],
+                            const int32_t b[3], const int32_t stride[3], double fraction,
+                            int32_t *out_centers, double *out_var, int64_t capacity) {
+    int32_t grid[3];
+    if (!aniso_sizes_ok(dims, b, stride, grid)) return -1;
+    if (!(fraction > 0.0) || fraction > 1.0) return -1;
+    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    const int64_t k = oracle_select_count(n, fraction);
+    if (k > capacity) return -2;
+    double *var = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    ranked_t *r = (ranked_t *)malloc(sizeof(ranked_t) * (n > 0 ? n : 1));
+    int64_t *chosen = (int64_t *)malloc(sizeof(int64_t) * (k > 0 ? k : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1],
+                      gz = g / ((int64_t)grid[0] * grid[1]);
+        aniso_block_variance(vol, dtype, dims, b, gx * stride[0], gy * stride[1], gz * stride[2],
+                             &r[g].key, &var[g]);
+        r[g].idx = g;
+    }
+    qsort(r, (size_t)n, sizeof(ranked_t), cmp_rank);
+    for (int64_t i = 0; i < k; ++i) chosen[i] = r[i].idx;
+    qsort(chosen, (size_t)k, sizeof(int64_t), cmp_i64);
+    for (int64_t i = 0; i < k; ++i) {
+        const int64_t g = chosen[i];
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1],
+                      gz = g / ((int64_t)grid[0] * grid[1]);
+        out_centers[3 * i + 0] = (int32_t)(gx * stride[0] + (b[0] - 1) / 2);
+        out_centers[3 * i + 1] = (int32_t)(gy * stride[1] + (b[1] - 1) / 2);
+        out_centers[3 * i + 2] = (int32_t)(gz * stride[2] + (b[2] - 1) / 2);
+        if (out_var) out_var[i] = var[g];
+    }
+    free(var), free(r), free(chosen);
+    return k;
+}
+
+/* Pearson correlation of the ref block at lowest corner (rx,ry,rz) and the
+   flt block at (fx,fy,fz), both bx*by*bz, two-pass FP64; 0 if either is flat. */
+static double aniso_ncc(const void *ref, const void *flt, int dtype, const int32_t dims[3],
+                        const int32_t b[3], int64_t rx, int64_t ry, int64_t rz, int64_t fx,
+                        int64_t fy, int64_t fz) {
+    const double nb = (double)b[0] * b[1] * b[2];
+    double st = 0.0, sf = 0.0;
+    for (int64_t z = 0; z < b[2]; ++z)
+        for (int64_t y = 0; y < b[1]; ++y)
+            for (int64_t x = 0; x < b[0]; ++x) {
+                st += voxel(ref, dtype, dims, rx + x, ry + y, rz + z);
+                sf += voxel(flt, dtype, dims, fx + x, fy + y, fz + z);
+            }
+    const double mt = st / nb, mf = sf / nb;
+    double a = 0.0, bb = 0.0, xx = 0.0;
+    for (int64_t z = 0; z < b[2]; ++z)
+        for (int64_t y = 0; y < b[1]; ++y)
+            for (int64_t x = 0; x < b[0]; ++x) {
+                const double t = voxel(ref, dtype, dims, rx + x, ry + y, rz + z) - mt;
+                const double f = voxel(flt, dtype, dims, fx + x, fy + y, fz + z) - mf;
+                a += t * t;
+                bb += f * f;
+                xx += t * f;
+            }
+    const double ab = a * bb;
+    if (!(ab > 0.0)) return 0.0;
+    return xx / sqrt(ab);
+}
+
+/* Exhaustive matching with per-axis block edges b[3] and half windows w[3]:
+   shift index ((dz+wz)(2wy+1) + (dy+wy))(2wx+1) + (dx+wx), smallest on ties. */
+int oracle_match_aniso(const void *ref, const void *flt, int dtype, const int32_t dims[3],
+                       const int32_t *centers, int64_t n, const int32_t b[3], const int32_t w[3],
+                       int32_t *disp, double *ncc, double *conf) {
+    for (int a = 0; a < 3; ++a)
+        if (b[a] < 1 || (b[a] % 2) == 0 || w[a] < 0) return -1;
+    const int64_t h[3] = {(b[0] - 1) / 2, (b[1] - 1) / 2, (b[2] - 1) / 2};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t c[3] = {centers[3 * k], centers[3 * k + 1], centers[3 * k + 2]};
+        int inside = 1;
+        int64_t lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            if (c[a] - h[a] < 0 || c[a] + h[a] > dims[a] - 1) inside = 0;
+            lo[a] = -w[a] > h[a] - c[a] ? -w[a] : h[a] - c[a];
+            hi[a] = w[a] < dims[a] - 1 - h[a] - c[a] ? w[a] : dims[a] - 1 - h[a] - c[a];
+        }
+        if (!inside) {
+            disp[3 * k] = disp[3 * k + 1] = disp[3 * k + 2] = 0;
+            ncc[k] = NAN;
+            conf[k] = 0.0;
+            continue;
+        }
+        double best = -INFINITY;
+        int64_t bd[3] = {0, 0, 0};
+        for (int64_t dz = lo[2]; dz <= hi[2]; ++dz)
+            for (int64_t dy = lo[1]; dy <= hi[1]; ++dy)
+                for (int64_t dx = lo[0]; dx <= hi[0]; ++dx) {
+                    const double v = aniso_ncc(ref, flt, dtype, dims, b, c[0] - h[0], c[1] - h[1],
+                                               c[2] - h[2], c[0] - h[0] + dx, c[1] - h[1] + dy,
+                                               c[2] - h[2] + dz);
+                    if (v > best) {
+                        best = v;
+                        bd[0] = dx, bd[1] = dy, bd[2] = dz;
+                    }
+                }
+        for (int a = 0; a < 3; ++a) disp[3 * k + a] = (int32_t)bd[a];
+        ncc[k] = best;
+        conf[k] = best > 0.0 ? best : 0.0;
+    }
+    return 0;
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

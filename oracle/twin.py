@@ -160,3 +160,62 @@ def structure_confidence(ref: np.ndarray, centers, block: int, conf) -> np.ndarr
         tr = j[:3].sum()
         out[k] = conf[k] * j / tr if tr > 0 else 0.0
     return out
+
+
+def select_aniso(vol: np.ndarray, block, stride, fraction: float) -> np.ndarray:
+    """Selection with per-axis block edges and strides, (x, y, z) triples."""
+    bx, by, bz = (int(v) for v in block)
+    sx, sy, sz = (int(v) for v in stride)
+    nz, ny, nx = vol.shape
+    ox, oy, oz = grid_origins(nx, bx, sx), grid_origins(ny, by, sy), grid_origins(nz, bz, sz)
+    blocks = sliding_window_view(vol, (bz, by, bx))[np.ix_(oz, oy, ox)]
+    blocks = blocks.reshape(len(oz) * len(oy) * len(ox), -1)
+    if vol.dtype == np.uint16:
+        v = blocks.astype(np.int64)
+        score = bx * by * bz * (v * v).sum(axis=1) - v.sum(axis=1) ** 2
+    else:
+        score = blocks.astype(np.float64).var(axis=1)
+    n = score.shape[0]
+    k = min(n, max(0, math.floor(0.5 + n * fraction)))
+    chosen = np.sort(np.lexsort((np.arange(n), -score))[:k])
+    gz, rem = np.divmod(chosen, len(oy) * len(ox))
+    gy, gx = np.divmod(rem, len(ox))
+    return np.stack([ox[gx] + (bx - 1) // 2, oy[gy] + (by - 1) // 2, oz[gz] + (bz - 1) // 2],
+                    axis=1).astype(np.int32)
+
+
+def match_aniso(ref: np.ndarray, flt: np.ndarray, centers, block, window):
+    """Search with per-axis block edges and half windows: every valid shift's
+    Pearson correlation, argmax by (largest NCC, smallest shift index)."""
+    b = np.array([int(v) for v in block])      # (x, y, z)
+    w = np.array([int(v) for v in window])
+    h = (b - 1) // 2
+    dims = np.array(ref.shape[::-1])
+    n = len(centers)
+    disp = np.zeros((n, 3), dtype=np.int32)
+    ncc = np.full(n, np.nan)
+    conf = np.zeros(n)
+    wins = sliding_window_view(flt, (b[2], b[1], b[0]))
+    for k, c in enumerate(np.asarray(centers, dtype=np.int64)):
+        if np.any(c - h < 0) or np.any(c + h > dims - 1):
+            continue
+        t = ref[c[2] - h[2]:c[2] + h[2] + 1, c[1] - h[1]:c[1] + h[1] + 1,
+                c[0] - h[0]:c[0] + h[0] + 1].astype(np.float64).ravel()
+        t -= t.mean()
+        lo = np.maximum(-w, h - c)
+        hi = np.minimum(w, dims - 1 - h - c)
+        sub = wins[c[2] - h[2] + lo[2]:c[2] - h[2] + hi[2] + 1,
+                   c[1] - h[1] + lo[1]:c[1] - h[1] + hi[1] + 1,
+                   c[0] - h[0] + lo[0]:c[0] - h[0] + hi[0] + 1].astype(np.float64)
+        f = sub.reshape(sub.shape[:3] + (-1,))
+        f = f - f.mean(axis=-1, keepdims=True)
+        den2 = float(t @ t) * np.einsum("...i,...i->...", f, f)
+        val = np.where(den2 > 0, (f @ t) / np.sqrt(np.where(den2 > 0, den2, 1.0)), 0.0)
+        # the sub-array is in increasing shift index (dz slowest, dx fastest)
+        i = int(np.flatnonzero(val.ravel() == val.max())[0])
+        iz, rem = divmod(i, val.shape[1] * val.shape[2])
+        iy, ix = divmod(rem, val.shape[2])
+        disp[k] = (lo[0] + ix, lo[1] + iy, lo[2] + iz)
+        ncc[k] = val.max()
+        conf[k] = max(0.0, ncc[k])
+    return disp, ncc, conf

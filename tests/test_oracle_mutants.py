@@ -55,11 +55,31 @@ MUTANTS_CONF = {
     "not_trace_normalised": ("out[6 * k + e] = tr > 0.0 ? conf[k] * j[e] / tr : 0.0;",
                              "out[6 * k + e] = tr > 0.0 ? conf[k] * j[e] : 0.0;"),
 }
+# mistakes in the per-axis (anisotropic) selection and search
+MUTANTS_ANISO = {
+    "aniso_window_axes_reversed": ("lo[a] = -w[a] > h[a] - c[a] ? -w[a] : h[a] - c[a];",
+                                   "lo[a] = -w[2 - a] > h[a] - c[a] ? -w[2 - a] : h[a] - c[a];"),
+    "aniso_centre_y_uses_x_half": (
+        "out_centers[3 * i + 1] = (int32_t)(gy * stride[1] + (b[1] - 1) / 2);",
+        "out_centers[3 * i + 1] = (int32_t)(gy * stride[1] + (b[0] - 1) / 2);"),
+    "aniso_key_uses_cube": ("*key = (double)((int64_t)b[0] * b[1] * b[2] * isq - isum * isum);",
+                            "*key = (double)((int64_t)b[0] * b[0] * b[0] * isq - isum * isum);"),
+    "aniso_z_origin_uses_x_stride": ("gx * stride[0], gy * stride[1], gz * stride[2],",
+                                     "gx * stride[0], gy * stride[1], gz * stride[0],"),
+    "aniso_rows_along_y_too_short": (
+        "for (int64_t y = 0; y < b[1]; ++y)\n            for (int64_t x = 0; x < b[0]; ++x) {\n                st +=",
+        "for (int64_t y = 0; y < b[0]; ++y)\n            for (int64_t x = 0; x < b[0]; ++x) {\n                st +="),
+    "aniso_tie_takes_last": (
+        "if (v > best) {\n                        best = v;\n                        bd[0]",
+        "if (v >= best) {\n                        best = v;\n                        bd[0]"),
+}
 PIN_FILES = {name: "test_oracle_pins.py" for name in MUTANTS}
+PIN_FILES.update({name: "test_oracle_aniso.py" for name in MUTANTS_ANISO})
 PIN_FILES.update({name: "test_oracle_confidence.py" for name in MUTANTS_CONF})
 PIN_FILES.update({name: "test_oracle_select_ex.py" for name in MUTANTS_EX})
 MUTANTS.update(MUTANTS_EX)
 MUTANTS.update(MUTANTS_CONF)
+MUTANTS.update(MUTANTS_ANISO)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
