@@ -185,6 +185,40 @@ nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype 
                                     float *conf, const void *workspace, size_t workspace_bytes,
                                     void *stream);
 
+/* Per-axis block and window sizes.  The paper's parameter list gives the
+ * half block size and the half search window separately for the three
+ * axes ("Deep Learning Model Architecture" section), so blocks need not be
+ * cubes.  block[3] = (bx, by, bz) are odd edges 1..15 (edge = 2 * half + 1),
+ * stride[3] the candidate-grid steps, window[3] = (wx, wy, wz) half windows
+ * 0..15.  Everything else is as in the cubic calls: the candidate grid per
+ * axis, K = floor(0.5 + N * fraction), variance ranking with ties to the
+ * lower grid index, centres in ascending grid index; displacements with
+ * |d_a| <= w_a that keep the block inside the volume, shift index
+ * ((dz+wz)(2wy+1) + (dy+wy))(2wx+1) + (dx+wx) breaking NCC ties, the flat
+ * and outside rules.
+ *
+ * nrr_aniso_workspace_bytes: device workspace of the selection (grid of
+ * block/stride) and of the search (block); either output may be NULL,
+ * stride may be NULL (then 1).
+ * nrr_select_blocks_aniso: as nrr_select_blocks with per-axis sizes.
+ * nrr_block_match_aniso: as nrr_block_match with per-axis sizes; the
+ * workspace holds the window statistics of the bx x by x bz block.
+ * Errors: INVALID_ARG, UNSUPPORTED (edge or half window above 15, window
+ * region larger than the LDS), BUFFER_TOO_SMALL, HIP. */
+nrr_status nrr_aniso_workspace_bytes(nrr_dtype dtype, const int32_t dims[3],
+                                     const int32_t block[3], const int32_t stride[3],
+                                     size_t *select_bytes, size_t *match_bytes);
+nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                   const int32_t block[3], const int32_t stride[3],
+                                   double fraction, int32_t *centers, int64_t capacity,
+                                   int64_t *k_out, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dtype,
+                                 const int32_t dims[3], const int32_t *centers, int64_t n,
+                                 const int32_t block[3], const int32_t window[3], int32_t *disp,
+                                 float *ncc, float *conf, void *workspace, size_t workspace_bytes,
+                                 void *stream);
+
 /* Directional confidence for the biomechanical solve.  The FEM update
  * equation weights each block's displacement by a confidence matrix S; the
  * paper gives no formula for it.  This returns, per block centred at

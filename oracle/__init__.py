@@ -68,6 +68,8 @@ def _load():
         lib.oracle_select_aniso.argtypes = [P, ctypes.c_int, P, P, P, f64, P, P, i64]
         lib.oracle_match_aniso.restype = ctypes.c_int
         lib.oracle_match_aniso.argtypes = [P, P, ctypes.c_int, P, P, i64, P, P, P, P, P]
+        lib.oracle_ncc_aniso_at.restype = ctypes.c_int
+        lib.oracle_ncc_aniso_at.argtypes = [P, P, ctypes.c_int, P, P, P, i64, P, P]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -226,6 +228,20 @@ def match_aniso(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block, wi
                                   _ptr(ncc), _ptr(conf)):
         raise ValueError("oracle_match_aniso rejected the arguments")
     return disp[:n], ncc[:n], conf[:n]
+
+
+def ncc_aniso_at(ref: np.ndarray, flt: np.ndarray, centers, disp, block) -> np.ndarray:
+    """FP64 NCC of each ref block and its flt block displaced by disp[k]
+    (per-axis block edges); NaN where a block leaves the volume."""
+    ref, dt = _vol(ref)
+    flt, _ = _vol(flt)
+    c = np.ascontiguousarray(centers, dtype=np.int32).reshape(-1, 3)
+    d = np.ascontiguousarray(disp, dtype=np.int32).reshape(-1, 3)
+    out = np.zeros(max(len(c), 1), dtype=np.float64)
+    if _load().oracle_ncc_aniso_at(_ptr(ref), _ptr(flt), dt, _ptr(_dims(ref)), _ptr(c), _ptr(d),
+                                   len(c), _ptr(_triple(block)), _ptr(out)):
+        raise ValueError("oracle_ncc_aniso_at rejected the arguments")
+    return out[:len(c)]
 
 
 def ncc_surface(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block: int, window: int):

@@ -669,6 +669,32 @@ int oracle_match_aniso(const void *ref, const void *flt, int dtype, const int32_
     return 0;
 }
 
+/* NCC of the ref block at centers[k] and the flt block displaced by
+   disp[k], per-axis block edges b[3]; NaN when either block leaves the
+   volume. */
+int oracle_ncc_aniso_at(const void *ref, const void *flt, int dtype, const int32_t dims[3],
+                        const int32_t *centers, const int32_t *disp, int64_t n,
+                        const int32_t b[3], double *out) {
+    for (int a = 0; a < 3; ++a)
+        if (b[a] < 1 || (b[a] % 2) == 0) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < n; ++k) {
+        int ok = 1;
+        int64_t lo_r[3], lo_f[3];
+        for (int a = 0; a < 3; ++a) {
+            const int64_t h = (b[a] - 1) / 2;
+            lo_r[a] = centers[3 * k + a] - h;
+            lo_f[a] = lo_r[a] + disp[3 * k + a];
+            if (lo_r[a] < 0 || lo_r[a] + b[a] > dims[a] || lo_f[a] < 0 || lo_f[a] + b[a] > dims[a])
+                ok = 0;
+        }
+        out[k] = ok ? aniso_ncc(ref, flt, dtype, dims, b, lo_r[0], lo_r[1], lo_r[2], lo_f[0],
+                                lo_f[1], lo_f[2])
+                    : NAN;
+    }
+    return 0;
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);

@@ -17,6 +17,7 @@ float32) on a HIP device; centres and displacements are ``(x, y, z)`` int32.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 __all__ = [
@@ -33,6 +34,9 @@ __all__ = [
     "block_match",
     "window_stats",
     "structure_confidence",
+    "aniso_workspace_bytes",
+    "select_blocks_aniso",
+    "block_match_aniso",
     "tune_match",
     "tuned_shape",
     "clear_tuning",
@@ -129,6 +133,11 @@ def load():
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
+        "nrr_aniso_workspace_bytes": (st, [ctypes.c_int, P, P, P, P, P]),
+        "nrr_select_blocks_aniso": (st, [P, ctypes.c_int, P, P, P, ctypes.c_double, P, I64, P, P,
+                                         ctypes.c_size_t, P]),
+        "nrr_block_match_aniso": (st, [P, P, ctypes.c_int, P, P, I64, P, P, P, P, P, P,
+                                       ctypes.c_size_t, P]),
         "nrr_structure_confidence": (st, [P, ctypes.c_int, P, P, I64, I32, P, P, P]),
         "nrr_tune_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, I32, P, P,
                                 P]),
@@ -321,6 +330,75 @@ def block_match(ref, flt, centers, block: int, window: int, workspace=None, out=
                                window, ctypes.c_void_p(disp.data_ptr()),
                                ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
+    return disp, ncc, conf
+
+
+def _triple(v) -> ctypes.Array:
+    t = (ctypes.c_int32 * 3)()
+    vals = [int(v)] * 3 if isinstance(v, int) else [int(x) for x in v]
+    if len(vals) != 3:
+        raise NrrError(1, "per-axis sizes are (x, y, z) triples")
+    for i in range(3):
+        t[i] = vals[i]
+    return t
+
+
+def aniso_workspace_bytes(dtype, dims, block, stride=None):
+    """(selection bytes, search bytes) for per-axis block edges and strides."""
+    lib = load()
+    sb, mb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib.nrr_aniso_workspace_bytes(dtype, _dims3(dims), _triple(block),
+                                         None if stride is None else _triple(stride),
+                                         ctypes.byref(sb), ctypes.byref(mb)))
+    return sb.value, mb.value
+
+
+def select_blocks_aniso(vol, block, stride, fraction: float, workspace=None):
+    """Variance-ranked selection with per-axis block edges and strides
+    ((x, y, z) triples): int32 [K, 3] centres in ascending grid index."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(vol)
+    b3, s3 = _triple(block), _triple(stride)
+    grid = [(dims[a] - b3[a]) // s3[a] + 1 for a in range(3)]
+    n = grid[0] * grid[1] * grid[2] if min(grid) > 0 else 0
+    kmax = max(int(math.floor(0.5 + n * fraction)), 1) if n > 0 else 1
+    out = torch.empty((kmax, 3), dtype=torch.int32, device=vol.device)
+    sel_bytes, _ = aniso_workspace_bytes(dt, dims, block, stride)
+    ws = _workspace(sel_bytes, vol.device, workspace)
+    kout = ctypes.c_int64()
+    _check(lib.nrr_select_blocks_aniso(ctypes.c_void_p(vol.data_ptr()), dt, _dims3(dims), b3, s3,
+                                       float(fraction), ctypes.c_void_p(out.data_ptr()),
+                                       out.shape[0], ctypes.byref(kout),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(vol)))
+    return out[:kout.value]
+
+
+def block_match_aniso(ref, flt, centers, block, window, workspace=None):
+    """Exhaustive NCC search with per-axis block edges and half windows;
+    returns (disp int32 [n,3], ncc f32 [n], conf f32 [n])."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    dt2, dims2 = _vol_info(flt)
+    if dt != dt2 or dims != dims2 or ref.device != flt.device:
+        raise NrrError(1, "ref and flt must share dtype, shape and device")
+    if centers.dtype != torch.int32 or centers.dim() != 2 or centers.shape[1] != 3 \
+            or not centers.is_contiguous() or centers.device != ref.device:
+        raise NrrError(1, "centers must be a contiguous int32 [n, 3] tensor on ref's device")
+    n = centers.shape[0]
+    disp = torch.empty((n, 3), dtype=torch.int32, device=ref.device)
+    ncc = torch.empty(n, dtype=torch.float32, device=ref.device)
+    conf = torch.empty(n, dtype=torch.float32, device=ref.device)
+    _, match_bytes = aniso_workspace_bytes(dt, dims, block)
+    ws = _workspace(match_bytes, ref.device, workspace)
+    _check(lib.nrr_block_match_aniso(ctypes.c_void_p(ref.data_ptr()),
+                                     ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
+                                     ctypes.c_void_p(centers.data_ptr()), n, _triple(block),
+                                     _triple(window), ctypes.c_void_p(disp.data_ptr()),
+                                     ctypes.c_void_p(ncc.data_ptr()),
+                                     ctypes.c_void_p(conf.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
     return disp, ncc, conf
 
 

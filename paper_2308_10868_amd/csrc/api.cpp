@@ -381,6 +381,128 @@ nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
                      L, st);
 }
 
+// ------------------------------------------------------- per-axis sizes
+
+namespace {
+
+// Per-axis block edges (odd, 1..15), strides (>= 1, may be NULL) and the
+// candidate grid they give.
+nrr_status check_box(const int32_t dims[3], const int32_t block[3], const int32_t stride[3],
+                     nrr::BoxGrid *G) {
+    if (!dims || !block) return fail(NRR_ERR_INVALID_ARG, "dims and block must be non-NULL");
+    for (int a = 0; a < 3; ++a) {
+        const int32_t b = block[a], st = stride ? stride[a] : 1;
+        if (b < 1 || b % 2 == 0)
+            return fail(NRR_ERR_INVALID_ARG, "block[%d] must be odd and >= 1 (got %d)", a, b);
+        if (b > 15) return fail(NRR_ERR_UNSUPPORTED, "block[%d] = %d: edges above 15 are not built",
+                                a, b);
+        if (st < 1) return fail(NRR_ERR_INVALID_ARG, "stride[%d] must be >= 1 (got %d)", a, st);
+        if (dims[a] < b)
+            return fail(NRR_ERR_INVALID_ARG, "dims[%d] = %d is smaller than block[%d] = %d", a,
+                        dims[a], a, b);
+        G->b[a] = b;
+        G->s[a] = st;
+        G->g[a] = (dims[a] - b) / st + 1;
+    }
+    return NRR_OK;
+}
+
+}  // namespace
+
+nrr_status nrr_aniso_workspace_bytes(nrr_dtype dtype, const int32_t dims[3],
+                                     const int32_t block[3], const int32_t stride[3],
+                                     size_t *select_bytes, size_t *match_bytes) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    nrr::BoxGrid G;
+    if ((s = check_box(dims, block, stride, &G)) != NRR_OK) return s;
+    if (select_bytes) *select_bytes = nrr::select_layout((int64_t)G.g[0] * G.g[1] * G.g[2]).total;
+    if (match_bytes) *match_bytes = nrr::stats_layout(dtype, dims, block, false).total;
+    return ok();
+}
+
+nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                   const int32_t block[3], const int32_t stride[3],
+                                   double fraction, int32_t *centers, int64_t capacity,
+                                   int64_t *k_out, void *workspace, size_t workspace_bytes,
+                                   void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    if (!k_out || !stride) return fail(NRR_ERR_INVALID_ARG, "k_out and stride must be non-NULL");
+    nrr::BoxGrid G;
+    if ((s = check_box(dims, block, stride, &G)) != NRR_OK) return s;
+    if (!(fraction > 0.0) || fraction > 1.0)
+        return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
+    const int64_t k = count_rule(n, fraction);
+    *k_out = k;
+    if (capacity < k)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "capacity %lld < K = %lld", (long long)capacity,
+                    (long long)k);
+    if (k == 0) return ok();
+    if (!vol || !centers || !workspace)
+        return fail(NRR_ERR_INVALID_ARG, "vol, centers and workspace must be non-NULL");
+    const size_t need = nrr::select_layout(n).total;
+    if (workspace_bytes < need)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes, need);
+    return hip_status(nrr::launch_select(vol, dtype, dims, G, k, centers, workspace,
+                                         static_cast<hipStream_t>(stream)),
+                      "nrr_select_blocks_aniso launch");
+}
+
+nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dtype,
+                                 const int32_t dims[3], const int32_t *centers, int64_t n,
+                                 const int32_t block[3], const int32_t window[3], int32_t *disp,
+                                 float *ncc, float *conf, void *workspace, size_t workspace_bytes,
+                                 void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    nrr::BoxGrid G;
+    if ((s = check_box(dims, block, nullptr, &G)) != NRR_OK) return s;
+    if (!window) return fail(NRR_ERR_INVALID_ARG, "window is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (window[a] < 0)
+            return fail(NRR_ERR_INVALID_ARG, "window[%d] must be >= 0 (got %d)", a, window[a]);
+    if (n < 0) return fail(NRR_ERR_INVALID_ARG, "n must be >= 0 (got %lld)", (long long)n);
+    if (n > INT32_MAX) return fail(NRR_ERR_UNSUPPORTED, "more than 2^31 - 1 blocks");
+    const char *why = nrr::aniso_unsupported_reason(block, window);
+    if (why)
+        return fail(NRR_ERR_UNSUPPORTED, "block (%d,%d,%d) window (%d,%d,%d): %s", block[0],
+                    block[1], block[2], window[0], window[1], window[2], why);
+    if (n == 0) return ok();
+    if (!ref || !flt || !centers || !disp || !ncc || !conf || !workspace)
+        return fail(NRR_ERR_INVALID_ARG, "array and workspace pointers must be non-NULL");
+    if ((int64_t)dims[0] * dims[1] * dims[2] >= (1ll << 40))
+        return fail(NRR_ERR_UNSUPPORTED, "volume too large");
+    const nrr::StatsLayout L = nrr::stats_layout(dtype, dims, block, false);
+    if (workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
+                    L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = nrr::launch_stats(flt, dtype, dims, block, false, workspace, st);
+    if (e != hipSuccess) return hip_status(e, "window statistics launch");
+    nrr::AnisoArgs a;
+    a.ref = ref;
+    a.flt = flt;
+    a.nx = dims[0];
+    a.ny = dims[1];
+    a.nz = dims[2];
+    a.centers = centers;
+    a.n = n;
+    for (int i = 0; i < 3; ++i) {
+        a.b[i] = block[i];
+        a.w[i] = window[i];
+    }
+    a.stats = workspace;
+    a.ox = L.ox;
+    a.oy = L.oy;
+    a.disp = disp;
+    a.ncc = ncc;
+    a.conf = conf;
+    a.cz = 0;
+    return hip_status(nrr::launch_match_aniso(dtype, a, st), "per-axis search launch");
+}
+
 nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int32_t dims[3],
                                     const int32_t *centers, int64_t n, int32_t block,
                                     const float *conf, float *out, void *stream) {

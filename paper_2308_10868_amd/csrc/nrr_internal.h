@@ -22,9 +22,22 @@ struct SelectLayout {
 };
 SelectLayout select_layout(int64_t n_candidates);
 
+// Candidate grid: per-axis block edge b, stride s and candidate count g
+// (x, y, z); centre of candidate i on an axis = i * s + (b - 1) / 2.
+struct BoxGrid {
+    int32_t b[3], s[3], g[3];
+};
+BoxGrid cubic_grid(int32_t block, int32_t stride, const int32_t grid[3]);
+// Ranking keys (selection order) of every candidate of G into keys[n].
+void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const BoxGrid &G,
+                 int64_t n, uint64_t *keys, hipStream_t stream);
+
 hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3], int32_t block,
                          int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
                          void *workspace, hipStream_t stream);
+hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                         const BoxGrid &G, int64_t k, int32_t *centers, void *workspace,
+                         hipStream_t stream);
 
 // Selection with a candidate mask and a connectivity pattern (0, 6, 18, 26)
 // for grids of at most kSelectExCand candidates; the number taken goes to
@@ -78,6 +91,11 @@ StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
 
 hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3], int32_t block,
                         void *workspace, hipStream_t stream);
+// Per-axis block (bx, by, bz); `pairs`: also the plane-pair volume (12-bit).
+StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], const int32_t block[3],
+                         bool pairs);
+hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                        const int32_t block[3], bool pairs, void *workspace, hipStream_t stream);
 
 // Directional confidence per block: out[n][6] = conf * J / trace(J).
 hipError_t launch_structure_conf(const void *ref, nrr_dtype dtype, const int32_t dims[3],
@@ -102,6 +120,26 @@ struct MatchArgs {
 
 // Returns 0 when supported, else a static reason string.
 const char *match_unsupported_reason(nrr_dtype dtype, int32_t block, int32_t window);
+
+// Search with per-axis block edges b and half windows w (x, y, z); `stats`
+// is the statistics table of the bx x by x bz block (no plane-pair volume);
+// cz is set by the launcher.
+struct AnisoArgs {
+    const void *ref;
+    const void *flt;
+    int32_t nx, ny, nz;
+    const int32_t *centers;
+    int64_t n;
+    int32_t b[3], w[3];
+    const void *stats;
+    int32_t ox, oy;
+    int32_t *disp;
+    float *ncc;
+    float *conf;
+    int32_t cz;
+};
+const char *aniso_unsupported_reason(const int32_t block[3], const int32_t window[3]);
+hipError_t launch_match_aniso(nrr_dtype dtype, const AnisoArgs &a, hipStream_t stream);
 
 // ------------------------------------------------------- batched matching
 // One parameter set of a batched search: its arguments (centres and outputs

@@ -25,22 +25,23 @@ struct SelectState {
     int64_t take_eq;  // how many candidates with key == kth are kept (lowest indices)
 };
 
-// One wavefront per candidate block: lanes take the block's b*b rows, sum
+// One wavefront per candidate block: lanes take the block's by*bz rows, sum
 // them exactly in integers and reduce across the wavefront.
 __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restrict__ vol, int nx,
-                                                        int ny, int b, int stride, int gx, int gy,
-                                                        int64_t n, uint64_t *__restrict__ keys) {
+                                                        int ny, BoxGrid G, int64_t n,
+                                                        uint64_t *__restrict__ keys) {
     const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (g >= n) return;  // whole wavefront leaves together
-    const int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
-    const int64_t x0 = ix * stride, y0 = iy * stride, z0 = iz * stride;
+    const int bx = G.b[0], by = G.b[1], bz = G.b[2];
+    const int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1], iz = g / ((int64_t)G.g[0] * G.g[1]);
+    const int64_t x0 = ix * G.s[0], y0 = iy * G.s[1], z0 = iz * G.s[2];
     uint64_t s = 0, q = 0;
-    for (int r = lane; r < b * b; r += 64) {
-        const int z = r / b, y = r - z * b;
+    for (int r = lane; r < by * bz; r += 64) {
+        const int z = r / by, y = r - z * by;
         const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
         uint32_t rs = 0, rq = 0;  // row sums: <= 15 * 4095^2 < 2^32
-        for (int x = 0; x < b; ++x) {
+        for (int x = 0; x < bx; ++x) {
             const uint32_t v = row[x];
             rs += v;
             rq += v * v;
@@ -52,27 +53,27 @@ __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restri
         s += __shfl_xor(s, off);
         q += __shfl_xor(q, off);
     }
-    if (lane == 0) keys[g] = (uint64_t)b * b * b * q - s * s;  // >= 0 by Cauchy-Schwarz
+    if (lane == 0) keys[g] = (uint64_t)bx * by * bz * q - s * s;  // >= 0 by Cauchy-Schwarz
 }
 
-// FP64 two-pass variance of the block at (x0, y0, z0), summed in z, y, x
-// order without contraction; returned as its (monotone) bit pattern.
-__device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int b,
-                                   int64_t x0, int64_t y0, int64_t z0) {
+// FP64 two-pass variance of the bx*by*bz block at (x0, y0, z0), summed in
+// z, y, x order without contraction; returned as its (monotone) bit pattern.
+__device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int bx, int by,
+                                   int bz, int64_t x0, int64_t y0, int64_t z0) {
 #pragma clang fp contract(off)
-    double nb = (double)b * b * b;
+    double nb = (double)bx * by * bz;
     double sum = 0.0;
-    for (int z = 0; z < b; ++z)
-        for (int y = 0; y < b; ++y) {
+    for (int z = 0; z < bz; ++z)
+        for (int y = 0; y < by; ++y) {
             const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            for (int x = 0; x < b; ++x) sum += (double)row[x];
+            for (int x = 0; x < bx; ++x) sum += (double)row[x];
         }
     double mean = sum / nb;
     double ss = 0.0;
-    for (int z = 0; z < b; ++z)
-        for (int y = 0; y < b; ++y) {
+    for (int z = 0; z < bz; ++z)
+        for (int y = 0; y < by; ++y) {
             const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            for (int x = 0; x < b; ++x) {
+            for (int x = 0; x < bx; ++x) {
                 double d = (double)row[x] - mean;
                 ss += d * d;
             }
@@ -81,29 +82,14 @@ __device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny
     return (uint64_t)__double_as_longlong(var);  // var >= +0: bit pattern is monotone
 }
 
-// Exact N*sum(x^2) - (sum x)^2 of the block at (x0, y0, z0), one thread.
-__device__ inline uint64_t key_u16(const uint16_t *__restrict__ vol, int nx, int ny, int b,
-                                   int64_t x0, int64_t y0, int64_t z0) {
-    uint64_t s = 0, q = 0;
-    for (int z = 0; z < b; ++z)
-        for (int y = 0; y < b; ++y) {
-            const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            for (int x = 0; x < b; ++x) {
-                const uint64_t v = row[x];
-                s += v;
-                q += v * v;
-            }
-        }
-    return (uint64_t)b * b * b * q - s * s;
-}
-
 __global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
-                                                        int ny, int b, int stride, int gx, int gy,
-                                                        int64_t n, uint64_t *__restrict__ keys) {
+                                                        int ny, BoxGrid G, int64_t n,
+                                                        uint64_t *__restrict__ keys) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
-    keys[g] = key_f32(vol, nx, ny, b, ix * stride, iy * stride, iz * stride);
+    int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1], iz = g / ((int64_t)G.g[0] * G.g[1]);
+    keys[g] = key_f32(vol, nx, ny, G.b[0], G.b[1], G.b[2], ix * G.s[0], iy * G.s[1],
+                      iz * G.s[2]);
 }
 
 // Count `d` (< 256) into the LDS histogram.  A wavefront whose counted lanes
@@ -252,9 +238,8 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint64_t *__restrict_
 // candidates of the workgroup's tile.
 __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ keys, int64_t n,
                                                  const SelectState *__restrict__ st,
-                                                 const int64_t *__restrict__ tiles, int gx,
-                                                 int gy, int stride, int h, int64_t k,
-                                                 int32_t *__restrict__ centers) {
+                                                 const int64_t *__restrict__ tiles, BoxGrid G,
+                                                 int64_t k, int32_t *__restrict__ centers) {
     constexpr int PER = kSelectTile / 256;
     __shared__ int64_t s_gt[256], s_eq[256];
     __shared__ int64_t s_base[2];
@@ -318,10 +303,11 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ ke
         bool keep = is_gt || (is_eq && eq_before < take);
         const int64_t pos = gt_before + (eq_before < take ? eq_before : take);
         if (keep && pos < k) {
-            int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
-            centers[3 * pos + 0] = (int32_t)(ix * stride + h);
-            centers[3 * pos + 1] = (int32_t)(iy * stride + h);
-            centers[3 * pos + 2] = (int32_t)(iz * stride + h);
+            const int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1],
+                          iz = g / ((int64_t)G.g[0] * G.g[1]);
+            centers[3 * pos + 0] = (int32_t)(ix * G.s[0] + (G.b[0] - 1) / 2);
+            centers[3 * pos + 1] = (int32_t)(iy * G.s[1] + (G.b[1] - 1) / 2);
+            centers[3 * pos + 2] = (int32_t)(iz * G.s[2] + (G.b[2] - 1) / 2);
         }
         gt_before += is_gt;
         eq_before += is_eq;
@@ -670,18 +656,23 @@ hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims
     const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
     SelectLayout L = select_layout(n);
     uint64_t *keys = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + L.keys_off);
-    if (dtype == NRR_U16)
-        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
-                           static_cast<const uint16_t *>(vol), dims[0], dims[1], block, stride,
-                           grid[0], grid[1], n, keys);
-    else
-        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           stream, static_cast<const float *>(vol), dims[0], dims[1], block,
-                           stride, grid[0], grid[1], n, keys);
+    const BoxGrid G = cubic_grid(block, stride, grid);
+    launch_keys(vol, dtype, dims, G, n, keys, stream);
     hipLaunchKernelGGL(k_select_ex, dim3(1), dim3(1024), 0, stream, keys, n, grid[0], grid[1],
                        grid[2], stride, (block - 1) / 2, dims[0], dims[1], mask, connectivity,
                        fraction, centers, k_device);
     return hipGetLastError();
+}
+
+// Ranking keys of every candidate of the grid G.
+void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const BoxGrid &G,
+                 int64_t n, uint64_t *keys, hipStream_t stream) {
+    if (dtype == NRR_U16)
+        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n, keys);
+    else
+        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           stream, static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
 }
 
 SelectLayout select_layout(int64_t n_candidates) {
@@ -694,30 +685,39 @@ SelectLayout select_layout(int64_t n_candidates) {
     return L;
 }
 
-hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3], int32_t block,
-                         int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
-                         void *workspace, hipStream_t stream) {
-    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+BoxGrid cubic_grid(int32_t block, int32_t stride, const int32_t grid[3]) {
+    BoxGrid G;
+    for (int a = 0; a < 3; ++a) {
+        G.b[a] = block;
+        G.s[a] = stride;
+        G.g[a] = grid[a];
+    }
+    return G;
+}
+
+hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                         const BoxGrid &G, int64_t k, int32_t *centers, void *workspace,
+                         hipStream_t stream) {
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
     SelectLayout L = select_layout(n);
     char *ws = static_cast<char *>(workspace);
     uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys_off);
     SelectState *st = reinterpret_cast<SelectState *>(ws + L.state_off);
     int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
-    const int64_t nblk = (n + 255) / 256;
-    if (dtype == NRR_U16)
-        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
-                           static_cast<const uint16_t *>(vol), dims[0], dims[1], block, stride,
-                           grid[0], grid[1], n, keys);
-    else
-        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)nblk), dim3(256), 0, stream,
-                           static_cast<const float *>(vol), dims[0], dims[1], block, stride,
-                           grid[0], grid[1], n, keys);
+    launch_keys(vol, dtype, dims, G, n, keys, stream);
     hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, st);
     hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
                        st, tiles);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
-                       tiles, grid[0], grid[1], stride, (block - 1) / 2, k, centers);
+                       tiles, G, k, centers);
     return hipGetLastError();
+}
+
+hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3], int32_t block,
+                         int32_t stride, const int32_t grid[3], int64_t k, int32_t *centers,
+                         void *workspace, hipStream_t stream) {
+    return launch_select(vol, dtype, dims, cubic_grid(block, stride, grid), k, centers, workspace,
+                         stream);
 }
 
 }  // namespace nrr

@@ -1,4 +1,5 @@
-// Per-voxel statistics of every b^3 block of the intra-operative volume.
+// Per-voxel statistics of every block (bx x by x bz, cubic for the plain
+// search) of the intra-operative volume.
 //
 // The NCC of the paper's similarity equation needs, for each displaced block
 // F, its mean and its spread sum (F - Fbar)^2.  Those depend only on the
@@ -13,12 +14,12 @@
 //        the block counts as flat when N q - s^2 <= 1e-12 * N q (FP64 cannot
 //        resolve a smaller relative spread from these sums).
 //
-// Layout of the outputs: dense [Oz][Oy][Ox] with O = dims - b + 1 (index =
+// Layout of the outputs: dense [Oz][Oy][Ox] with O = dims - block + 1 (index =
 // lowest corner of the block).  Work decomposition: a workgroup owns a
 // 64 x 4 tile of (x, y) origins and a run of zc origin planes; each input
 // plane is staged in LDS (fetched two planes ahead) and summed along x
 // (sliding windows over 4-wide segments) then along y; the per-plane sums of
-// the last b planes sit in a small LDS ring, and the z sum slides exactly
+// the last bz planes sit in a small LDS ring, and the z sum slides exactly
 // (integers) or is re-added from the ring (floating point).  The next plane's patch is fetched into registers
 // while the current one is summed (double-buffered LDS patch).
 #include <hip/hip_runtime.h>
@@ -40,13 +41,14 @@ constexpr int PER = (PATCH + 255) / 256;  // patch elements staged per thread
 // the plane being summed.
 template <bool SLIDE, typename V, typename A, typename AQ, typename AS, typename AQQ,
           typename Src, typename Conv, typename Emit>
-__device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int b,
+__device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int bx,
+                                  int by, int bz,
                                   int ox, int oy, int oz, int zc, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
                                   A *ringP, AQ *ringQ, Conv conv, Emit emit) {
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;  // output (tx, ty)
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
-    const int ph = TY + b - 1, pw = TX + b - 1;
-    const int zend = min(z0 + zc + b - 1, nz);  // input planes [z0, zend)
+    const int ph = TY + by - 1, pw = TX + bx - 1;
+    const int zend = min(z0 + zc + bz - 1, nz);  // input planes [z0, zend)
     // this thread's patch elements: fixed offsets inside a plane
     int goff[PER];
     bool gok[PER];
@@ -82,7 +84,7 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
             const V *row = pc + r * pw + xs;
             A sv = 0;
             AQ qv = 0;
-            for (int k = 0; k < b; ++k) {
+            for (int k = 0; k < bx; ++k) {
                 const A v = (A)row[k];
                 sv += v;
                 qv += (AQ)(v * v);
@@ -91,7 +93,7 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
             rq[r * TX + xs] = qv;
 #pragma unroll
             for (int u = 1; u < SEG; ++u) {
-                const A vin = (A)row[u + b - 1], vout = (A)row[u - 1];
+                const A vin = (A)row[u + bx - 1], vout = (A)row[u - 1];
                 sv += vin - vout;
                 qv += (AQ)(vin * vin) - (AQ)(vout * vout);
                 rs[r * TX + xs + u] = sv;
@@ -101,27 +103,27 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
         __syncthreads();
         A P = 0;  // then along y
         AQ Q = 0;
-        for (int k = 0; k < b; ++k) {
+        for (int k = 0; k < by; ++k) {
             P += rs[(ty + k) * TX + tx];
             Q += rq[(ty + k) * TX + tx];
         }
-        const int slot = (zi - z0) % b;
+        const int slot = (zi - z0) % bz;
         if constexpr (SLIDE) {
-            const bool full = zi - z0 >= b;  // the slot holds the plane leaving the block
+            const bool full = zi - z0 >= bz;  // the slot holds the plane leaving the block
             S += (AS)P - (full ? (AS)ringP[slot * 256 + tid] : (AS)0);
             QQ += (AQQ)Q - (full ? (AQQ)ringQ[slot * 256 + tid] : (AQQ)0);
         }
         ringP[slot * 256 + tid] = P;
         ringQ[slot * 256 + tid] = Q;
-        if (zi - z0 >= b - 1) {  // the last b plane sums give the block sums
-            const int z = zi - b + 1, x = x0 + tx, y = y0 + ty;
+        if (zi - z0 >= bz - 1) {  // the last bz plane sums give the block sums
+            const int z = zi - bz + 1, x = x0 + tx, y = y0 + ty;
             if (x < ox && y < oy && z < oz) {
                 AS sb = S;
                 AQQ qb = QQ;
                 if constexpr (!SLIDE) {
                     sb = 0;
                     qb = 0;
-                    for (int k = 0; k < b; ++k) {
+                    for (int k = 0; k < bz; ++k) {
                         sb += (AS)ringP[k * 256 + tid];
                         qb += (AQQ)ringQ[k * 256 + tid];
                     }
@@ -140,18 +142,19 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
 }
 
 __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ flt, int nx,
-                                                   int ny, int nz, int b, int ox, int oy, int oz,
-                                                   int zc, StatU16 *__restrict__ out) {
+                                                   int ny, int nz, int bx, int by, int bz, int ox,
+                                                   int oy, int oz, int zc,
+                                                   StatU16 *__restrict__ out) {
     __shared__ int32_t patch[2 * PATCH + 256];
     __shared__ int32_t rs[PH * TX];
     __shared__ uint32_t rq[PH * TX];
-    // ring of the last b per-plane sums, [b][256] each (dynamic LDS)
+    // ring of the last bz per-plane sums, [bz][256] each (dynamic LDS)
     extern __shared__ __align__(16) unsigned char dyn_u16[];
     int32_t *ringP = reinterpret_cast<int32_t *>(dyn_u16);
-    uint32_t *ringQ = reinterpret_cast<uint32_t *>(dyn_u16 + (size_t)b * 256 * 4);
-    const int64_t n = (int64_t)b * b * b;
+    uint32_t *ringQ = reinterpret_cast<uint32_t *>(dyn_u16 + (size_t)bz * 256 * 4);
+    const int64_t n = (int64_t)bx * by * bz;
     stats_body<true, int32_t, int32_t, uint32_t, int32_t, uint64_t>(
-        flt, nx, ny, nz, b, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
         [](uint16_t v) { return (int32_t)v - 2048; },
         [&](int64_t o, int32_t S, uint64_t QQ) {
             const int64_t var = n * (int64_t)QQ - (int64_t)S * S;
@@ -164,17 +167,18 @@ __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt, int nx, int ny,
-                                                   int nz, int b, int ox, int oy, int oz, int zc,
-                                                   StatF32 *__restrict__ out) {
+                                                   int nz, int bx, int by, int bz, int ox, int oy,
+                                                   int oz, int zc, StatF32 *__restrict__ out) {
     __shared__ float patch[2 * PATCH + 256];
     __shared__ double rs[PH * TX];
     __shared__ double rq[PH * TX];
     extern __shared__ __align__(16) unsigned char dyn_f32[];
     double *ringP = reinterpret_cast<double *>(dyn_f32);
-    double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)b * 256 * 8);
-    const double n = (double)b * b * b;
+    double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)bz * 256 * 8);
+    const double n = (double)bx * by * bz;
     stats_body<false, float, double, double, double, double>(
-        flt, nx, ny, nz, b, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, [](float v) { return v; },
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
+        [](float v) { return v; },
         [&](int64_t o, double S, double QQ) {
             const double nq = n * QQ;
             const double var = nq - S * S;
@@ -287,27 +291,34 @@ hipError_t launch_structure_conf(const void *ref, nrr_dtype dtype, const int32_t
     return hipGetLastError();
 }
 
-StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block) {
+StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], const int32_t block[3],
+                         bool pairs) {
     StatsLayout L;
-    L.ox = dims[0] - block + 1;
-    L.oy = dims[1] - block + 1;
-    L.oz = dims[2] - block + 1;
+    L.ox = dims[0] - block[0] + 1;
+    L.oy = dims[1] - block[1] + 1;
+    L.oz = dims[2] - block[2] + 1;
     // slack after the table: the search reads whole tiles of records, up to
     // kTileSlack rows and columns past the last valid origin
     const size_t nvox = (size_t)L.ox * L.oy * L.oz + (size_t)kTileSlack * (L.ox + 1);
     L.total = align_up(nvox * (dtype == NRR_U16 ? sizeof(StatU16) : sizeof(StatF32)), 256);
     L.pair_off = 0;
-    if (dtype == NRR_U16) {  // + slack: staging reads whole 4-word row chunks
+    if (pairs && dtype == NRR_U16) {  // + slack: staging reads whole 4-word row chunks
         L.pair_off = L.total;
         L.total += align_up(((size_t)dims[0] * dims[1] * dims[2] + 64) * 4, 256);
     }
     return L;
 }
 
-hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3], int32_t block,
-                        void *workspace, hipStream_t stream) {
-    StatsLayout L = stats_layout(dtype, dims, block);
+StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block) {
+    const int32_t b3[3] = {block, block, block};
+    return stats_layout(dtype, dims, b3, true);
+}
+
+hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                        const int32_t block[3], bool pairs, void *workspace, hipStream_t stream) {
+    StatsLayout L = stats_layout(dtype, dims, block, pairs);
     char *ws = static_cast<char *>(workspace);
+    const int bx = block[0], by = block[1], bz = block[2];
     // origin planes per workgroup: ZC, fewer when that leaves the device with
     // too few workgroups (small volumes), never below 4
     const int64_t per_slab = (int64_t)((L.ox + TX - 1) / TX) * ((L.oy + TY - 1) / TY);
@@ -316,19 +327,28 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
     if (dtype == NRR_U16) {
-        hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)block * 256 * 8, stream,
-                           static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], block,
-                           L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws));
-        const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
-        const int64_t groups = (nvox + 1023) / 1024;
-        hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
-                           static_cast<const uint16_t *>(flt), nvox, (int64_t)dims[0] * dims[1],
-                           reinterpret_cast<uint32_t *>(ws + L.pair_off));
+        hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)bz * 256 * 8, stream,
+                           static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], bx, by,
+                           bz, L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws));
+        if (L.pair_off) {
+            const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+            const int64_t groups = (nvox + 1023) / 1024;
+            hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
+                               static_cast<const uint16_t *>(flt), nvox,
+                               (int64_t)dims[0] * dims[1],
+                               reinterpret_cast<uint32_t *>(ws + L.pair_off));
+        }
     } else
-        hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)block * 256 * 16, stream,
-                           static_cast<const float *>(flt), dims[0], dims[1], dims[2], block,
+        hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
+                           static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
                            L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
     return hipGetLastError();
+}
+
+hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3], int32_t block,
+                        void *workspace, hipStream_t stream) {
+    const int32_t b3[3] = {block, block, block};
+    return launch_stats(flt, dtype, dims, b3, true, workspace, stream);
 }
 
 }  // namespace nrr

@@ -225,3 +225,47 @@ def test_structure_confidence_validation(lib):
     assert f(p, 0, dims, p, -1, 7, p, p, None) == 1     # negative count
     assert f(p, 0, dims, None, 4, 7, p, p, None) == 1   # null centres
     assert f(None, 0, dims, None, 0, 7, None, None, None) == 0  # n == 0: no-op
+
+
+def test_aniso_validation(lib):
+    import ctypes
+
+    buf = (ctypes.c_byte * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    t3 = lambda *v: (ctypes.c_int32 * 3)(*v)  # noqa: E731
+    dims = t3(40, 30, 20)
+    ws = lib.nrr_aniso_workspace_bytes
+    ws.restype = ctypes.c_int
+    ws.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                   ctypes.c_void_p, ctypes.c_void_p]
+    sb, mb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert ws(0, dims, t3(5, 3, 7), t3(5, 3, 7), ctypes.byref(sb), ctypes.byref(mb)) == 0
+    # u16 search table: one 8-byte record per origin plus the tile slack rows
+    ox, oy, oz = 40 - 5 + 1, 30 - 3 + 1, 20 - 7 + 1
+    assert mb.value >= (ox * oy * oz) * 8 and mb.value % 256 == 0
+    assert sb.value >= (8 * 10 * 2) * 8  # one 8-byte key per candidate
+    assert ws(0, dims, t3(4, 3, 3), None, None, None) == 1     # even edge
+    assert ws(0, dims, t3(17, 3, 3), None, None, None) == 4    # edge above 15
+    assert ws(0, t3(40, 30, 9), t3(3, 3, 11), None, None, None) == 1  # larger than the volume
+    m = lib.nrr_block_match_aniso
+    m.restype = ctypes.c_int
+    m.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                  ctypes.c_size_t, ctypes.c_void_p]
+    assert m(p, p, 0, dims, p, 4, t3(5, 3, 3), t3(2, -1, 2), p, p, p, p, 1 << 30, None) == 1
+    assert m(p, p, 0, dims, p, 4, t3(5, 3, 3), t3(2, 16, 2), p, p, p, p, 1 << 30, None) == 4
+    assert m(p, p, 0, dims, p, 4, t3(5, 3, 3), t3(2, 1, 2), p, p, p, p, 16, None) == 2
+    assert m(None, None, 0, dims, None, 0, t3(5, 3, 3), t3(2, 1, 2), None, None, None, None, 0,
+             None) == 0  # n == 0: no-op
+    sel = lib.nrr_select_blocks_aniso
+    sel.restype = ctypes.c_int
+    sel.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                    ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    k = ctypes.c_int64()
+    assert sel(p, 0, dims, t3(5, 3, 7), t3(5, 3, 0), 0.5, p, 1000, ctypes.byref(k), p, 1 << 30,
+               None) == 1  # zero stride
+    assert sel(p, 0, dims, t3(5, 3, 7), t3(5, 3, 7), 0.5, p, 1, ctypes.byref(k), p, 1 << 30,
+               None) == 2  # capacity
+    assert k.value == int(0.5 + 8 * 10 * 2 * 0.5)

@@ -1,0 +1,155 @@
+"""GPU: selection and search with per-axis block edges, strides and half
+windows, against the oracle: the selection bit-exact, the search under the
+parity rule (the oracle's argmax, or a displacement whose oracle NCC is
+within 1e-5 of it; reported NCC within 1e-5 of the oracle's at the GPU's
+displacement)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2308_10868_amd as nrr
+from paper_2308_10868_amd import synth
+from tests.gpu_util import NCC_TOL, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nrr.load()
+    return torch
+
+
+def check_aniso(ref, flt, centers, block, window, dg, ng, cg, label=""):
+    d_o, n_o, _ = oracle.match_aniso(ref, flt, centers, block, window)
+    v = oracle.ncc_aniso_at(ref, flt, centers, dg, block)
+    differ = 0
+    for k in range(len(centers)):
+        if np.isnan(n_o[k]):
+            assert np.isnan(ng[k]) and cg[k] == 0 and np.all(dg[k] == 0), (label, k)
+            continue
+        assert np.all(np.abs(dg[k]) <= np.array(window)), (label, k, dg[k])
+        assert not np.isnan(v[k]), ("GPU displacement invalid", label, k, dg[k])
+        assert n_o[k] - v[k] < NCC_TOL, ("argmax gap", label, k, dg[k], d_o[k], n_o[k] - v[k])
+        assert abs(float(ng[k]) - v[k]) <= NCC_TOL, ("ncc", label, k, ng[k], v[k])
+        assert abs(float(cg[k]) - max(0.0, v[k])) <= NCC_TOL, ("conf", label, k)
+        differ += int(not np.array_equal(dg[k], d_o[k]))
+    return differ
+
+
+def run(torch, ref, flt, centers, block, window):
+    r, f = to_dev(ref), to_dev(flt)
+    c = torch.from_numpy(np.ascontiguousarray(centers, dtype=np.int32)).cuda()
+    d, n, cf = nrr.block_match_aniso(r, f, c, block, window)
+    torch.cuda.synchronize()
+    return to_host(d), to_host(n), to_host(cf)
+
+
+SHAPES = [((3, 5, 1), (2, 2, 1), (2, 1, 0)),
+          ((5, 1, 3), (3, 1, 2), (0, 2, 1)),
+          ((7, 5, 3), (4, 3, 2), (3, 2, 1)),
+          ((9, 3, 5), (5, 2, 3), (4, 0, 3)),
+          ((1, 1, 1), (1, 1, 1), (1, 1, 1))]
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+@pytest.mark.parametrize("b,s,w", SHAPES)
+def test_select_bit_exact(torch_dev, dtype, b, s, w):
+    for seed in range(2):
+        p = synth.gen_random(60 + seed, (23, 19, 17), dtype, smooth=1.0)
+        say("aniso select", dtype, b, s, seed)
+        want, _ = oracle.select_aniso(p.ref, b, s, 0.4)
+        got = to_host(nrr.select_blocks_aniso(to_dev(p.ref), b, s, 0.4))
+        torch_dev.cuda.synchronize()
+        assert np.array_equal(got, want), (dtype, b, s, seed)
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+@pytest.mark.parametrize("b,s,w", SHAPES)
+def test_search_parity_with_border_blocks(torch_dev, dtype, b, s, w):
+    p = synth.gen_random(70, (23, 19, 17), dtype, smooth=1.0)
+    cen, _ = oracle.select_aniso(p.ref, b, s, 0.5)
+    h = [(v - 1) // 2 for v in b]
+    extra = np.array([[h[0], h[1], h[2]], [22 - h[0], 18 - h[1], 16 - h[2]],
+                      [h[0] - 1, 5, 5], [22, 18, 16]], np.int32)  # corners and outside
+    extra = extra[np.all(extra >= 0, axis=1)]
+    cen = np.concatenate([cen, extra]).astype(np.int32)
+    say("aniso match", dtype, b, w, len(cen))
+    dg, ng, cg = run(torch_dev, p.ref, p.flt, cen, b, w)
+    check_aniso(p.ref, p.flt, cen, b, w, dg, ng, cg, (dtype, b, w))
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_wide_windows_take_several_z_runs(torch_dev, dtype):
+    """Half windows up to 15 and 15-voxel edges: the window region is staged
+    in several runs of displacement planes."""
+    p = synth.gen_random(71, (48, 44, 40), dtype, smooth=1.5)
+    for b, w in [((15, 13, 11), (15, 6, 9)), ((5, 15, 7), (2, 15, 15)), ((11, 3, 15), (12, 2, 4))]:
+        h = [(v - 1) // 2 for v in b]
+        rng = np.random.default_rng(0)
+        cen = np.stack([rng.integers(h[a], (48, 44, 40)[a] - h[a], 12) for a in range(3)], axis=1)
+        say("aniso wide", dtype, b, w)
+        dg, ng, cg = run(torch_dev, p.ref, p.flt, cen.astype(np.int32), b, w)
+        check_aniso(p.ref, p.flt, cen, b, w, dg, ng, cg, (dtype, b, w))
+
+
+def test_flat_and_shift_cases(torch_dev):
+    ref = synth.gen_random(72, (20, 18, 16), "f32", smooth=1.0).ref
+    shift = (2, 1, 0)
+    flt = np.roll(ref, (shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    cen = np.array([[8, 8, 8], [10, 7, 6], [9, 9, 9]], np.int32)
+    say("aniso shift")
+    dg, ng, _ = run(torch_dev, ref, flt, cen, (5, 3, 3), (3, 1, 0))
+    assert np.all(dg == shift) and np.allclose(ng, 1.0, atol=1e-6)
+    flat = np.full_like(ref, 7.0)
+    say("aniso flat")
+    dg, ng, cg = run(torch_dev, ref, flat, cen, (3, 5, 3), (2, 1, 3))
+    h = np.array([1, 2, 1])
+    assert np.array_equal(dg, np.maximum(-np.array([2, 1, 3]), h - cen))
+    assert np.all(ng == 0) and np.all(cg == 0)
+
+
+def test_cubic_sizes_match_the_cubic_search(torch_dev):
+    """Equal per-axis sizes: the same displacements as the tuned cubic path
+    (both are held to the oracle; on generic data their argmax agree)."""
+    import torch
+
+    p = synth.gen_mri_u16(seed=2, dims=(64, 64, 40))
+    r, f = to_dev(p.ref), to_dev(p.flt)
+    c = nrr.select_blocks(r, 7, 7, 0.5)
+    say("aniso vs cubic", c.shape[0])
+    d1, n1, _ = nrr.block_match(r, f, c, 7, 5)
+    d2, n2, _ = nrr.block_match_aniso(r, f, c, (7, 7, 7), (5, 5, 5))
+    torch.cuda.synchronize()
+    same = np.all(to_host(d1) == to_host(d2), axis=1)
+    assert same.mean() > 0.99
+    assert np.abs(to_host(n1) - to_host(n2))[same].max() < 2 * NCC_TOL
+
+
+def test_mri_sized_case(torch_dev):
+    """The MRI pair at 128 x 128 x 62 with an axial-thick block."""
+    p = synth.gen_mri_u16(seed=5, dims=(128, 128, 62))
+    b, s, w = (7, 7, 5), (7, 7, 5), (6, 6, 3)
+    r, f = to_dev(p.ref), to_dev(p.flt)
+    c = nrr.select_blocks_aniso(r, b, s, 0.25)
+    want, _ = oracle.select_aniso(p.ref, b, s, 0.25)
+    assert np.array_equal(to_host(c), want)
+    say("aniso mri", c.shape[0])
+    d, n, cf = nrr.block_match_aniso(r, f, c, b, w)
+    import torch
+
+    torch.cuda.synchronize()
+    sample = np.arange(0, len(want), max(1, len(want) // 150))
+    check_aniso(p.ref, p.flt, want[sample], b, w, to_host(d)[sample], to_host(n)[sample],
+                to_host(cf)[sample], "mri")

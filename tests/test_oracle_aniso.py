@@ -114,3 +114,22 @@ def test_flat_volume_takes_smallest_shift_index():
     lo = np.maximum(-np.array(w), h - cen)
     assert np.array_equal(d, lo) and np.all(n == 0.0) and np.all(f == 0.0)
     assert np.all(cen + h <= dims - 1)
+
+
+def test_ncc_at_agrees_with_the_search():
+    """The NCC at the search's displacement is the reported one, every valid
+    displacement in the window scores no higher, and leaving the volume
+    gives NaN."""
+    p = synth.gen_random(8, (14, 12, 11), "f32", smooth=1.0)
+    b, w = (5, 3, 3), (2, 1, 2)
+    cen = np.array([[6, 5, 5], [2, 1, 1], [9, 8, 7]], np.int32)
+    d, n, _ = oracle.match_aniso(p.ref, p.flt, cen, b, w)
+    assert np.array_equal(oracle.ncc_aniso_at(p.ref, p.flt, cen, d, b), n)
+    for dz in range(-w[2], w[2] + 1):
+        for dy in range(-w[1], w[1] + 1):
+            for dx in range(-w[0], w[0] + 1):
+                v = oracle.ncc_aniso_at(p.ref, p.flt, cen, np.tile([dx, dy, dz], (3, 1)), b)
+                ok = ~np.isnan(v)
+                assert np.all(v[ok] <= n[ok])
+    far = oracle.ncc_aniso_at(p.ref, p.flt, cen, np.tile([0, 0, 9], (3, 1)), b)
+    assert np.all(np.isnan(far))
