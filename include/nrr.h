@@ -218,6 +218,20 @@ nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dty
                                  const int32_t block[3], const int32_t window[3], int32_t *disp,
                                  float *ncc, float *conf, void *workspace, size_t workspace_bytes,
                                  void *stream);
+/* The two halves of nrr_block_match_aniso, for callers that search several
+ * block sets against one moving volume: nrr_window_stats_aniso fills the
+ * workspace with the statistics of the bx x by x bz block of `flt`;
+ * nrr_block_match_aniso_prepared searches with that workspace (which must
+ * come from the same flt, dtype, dims and block). */
+nrr_status nrr_window_stats_aniso(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                                  const int32_t block[3], void *workspace,
+                                  size_t workspace_bytes, void *stream);
+nrr_status nrr_block_match_aniso_prepared(const void *ref, const void *flt, nrr_dtype dtype,
+                                          const int32_t dims[3], const int32_t *centers,
+                                          int64_t n, const int32_t block[3],
+                                          const int32_t window[3], int32_t *disp, float *ncc,
+                                          float *conf, const void *workspace,
+                                          size_t workspace_bytes, void *stream);
 
 /* Directional confidence for the biomechanical solve.  The FEM update
  * equation weights each block's displacement by a confidence matrix S; the

@@ -37,6 +37,7 @@ __all__ = [
     "aniso_workspace_bytes",
     "select_blocks_aniso",
     "block_match_aniso",
+    "window_stats_aniso",
     "tune_match",
     "tuned_shape",
     "clear_tuning",
@@ -138,6 +139,9 @@ def load():
                                          ctypes.c_size_t, P]),
         "nrr_block_match_aniso": (st, [P, P, ctypes.c_int, P, P, I64, P, P, P, P, P, P,
                                        ctypes.c_size_t, P]),
+        "nrr_block_match_aniso_prepared": (st, [P, P, ctypes.c_int, P, P, I64, P, P, P, P, P, P,
+                                                ctypes.c_size_t, P]),
+        "nrr_window_stats_aniso": (st, [P, ctypes.c_int, P, P, P, ctypes.c_size_t, P]),
         "nrr_structure_confidence": (st, [P, ctypes.c_int, P, P, I64, I32, P, P, P]),
         "nrr_tune_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, I32, P, P,
                                 P]),
@@ -374,9 +378,24 @@ def select_blocks_aniso(vol, block, stride, fraction: float, workspace=None):
     return out[:kout.value]
 
 
-def block_match_aniso(ref, flt, centers, block, window, workspace=None):
+def window_stats_aniso(flt, block, workspace=None):
+    """Window statistics of the per-axis block of `flt` into a workspace for
+    ``block_match_aniso(..., prepared=True)``; returns the workspace."""
+    lib = load()
+    dt, dims = _vol_info(flt)
+    _, match_bytes = aniso_workspace_bytes(dt, dims, block)
+    ws = _workspace(match_bytes, flt.device, workspace)
+    _check(lib.nrr_window_stats_aniso(ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
+                                      _triple(block), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream(flt)))
+    return ws
+
+
+def block_match_aniso(ref, flt, centers, block, window, workspace=None, out=None,
+                      prepared: bool = False):
     """Exhaustive NCC search with per-axis block edges and half windows;
-    returns (disp int32 [n,3], ncc f32 [n], conf f32 [n])."""
+    returns (disp int32 [n,3], ncc f32 [n], conf f32 [n]).  With
+    ``prepared=True`` ``workspace`` must hold ``window_stats_aniso(flt, block)``."""
     torch = _torch()
     lib = load()
     dt, dims = _vol_info(ref)
@@ -387,18 +406,22 @@ def block_match_aniso(ref, flt, centers, block, window, workspace=None):
             or not centers.is_contiguous() or centers.device != ref.device:
         raise NrrError(1, "centers must be a contiguous int32 [n, 3] tensor on ref's device")
     n = centers.shape[0]
-    disp = torch.empty((n, 3), dtype=torch.int32, device=ref.device)
-    ncc = torch.empty(n, dtype=torch.float32, device=ref.device)
-    conf = torch.empty(n, dtype=torch.float32, device=ref.device)
+    if out is None:
+        disp = torch.empty((n, 3), dtype=torch.int32, device=ref.device)
+        ncc = torch.empty(n, dtype=torch.float32, device=ref.device)
+        conf = torch.empty(n, dtype=torch.float32, device=ref.device)
+    else:
+        disp, ncc, conf = out
+    if prepared and workspace is None:
+        raise NrrError(1, "prepared=True needs the workspace window_stats_aniso() filled")
     _, match_bytes = aniso_workspace_bytes(dt, dims, block)
     ws = _workspace(match_bytes, ref.device, workspace)
-    _check(lib.nrr_block_match_aniso(ctypes.c_void_p(ref.data_ptr()),
-                                     ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
-                                     ctypes.c_void_p(centers.data_ptr()), n, _triple(block),
-                                     _triple(window), ctypes.c_void_p(disp.data_ptr()),
-                                     ctypes.c_void_p(ncc.data_ptr()),
-                                     ctypes.c_void_p(conf.data_ptr()),
-                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
+    fn = lib.nrr_block_match_aniso_prepared if prepared else lib.nrr_block_match_aniso
+    _check(fn(ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()), dt,
+              _dims3(dims), ctypes.c_void_p(centers.data_ptr()), n, _triple(block),
+              _triple(window), ctypes.c_void_p(disp.data_ptr()), ctypes.c_void_p(ncc.data_ptr()),
+              ctypes.c_void_p(conf.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+              _stream(ref)))
     return disp, ncc, conf
 
 

@@ -450,11 +450,14 @@ nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32
                       "nrr_select_blocks_aniso launch");
 }
 
-nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dtype,
-                                 const int32_t dims[3], const int32_t *centers, int64_t n,
-                                 const int32_t block[3], const int32_t window[3], int32_t *disp,
-                                 float *ncc, float *conf, void *workspace, size_t workspace_bytes,
-                                 void *stream) {
+namespace {
+
+// Validation shared by the per-axis search entry points; fills the layout.
+nrr_status check_aniso(const void *ref, const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                       const int32_t *centers, int64_t n, const int32_t block[3],
+                       const int32_t window[3], const int32_t *disp, const float *ncc,
+                       const float *conf, const void *workspace, size_t workspace_bytes,
+                       nrr::StatsLayout *L) {
     nrr_status s = check_dtype(dtype);
     if (s != NRR_OK) return s;
     nrr::BoxGrid G;
@@ -469,18 +472,22 @@ nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dty
     if (why)
         return fail(NRR_ERR_UNSUPPORTED, "block (%d,%d,%d) window (%d,%d,%d): %s", block[0],
                     block[1], block[2], window[0], window[1], window[2], why);
-    if (n == 0) return ok();
+    if (n == 0) return NRR_OK;
     if (!ref || !flt || !centers || !disp || !ncc || !conf || !workspace)
         return fail(NRR_ERR_INVALID_ARG, "array and workspace pointers must be non-NULL");
     if ((int64_t)dims[0] * dims[1] * dims[2] >= (1ll << 40))
         return fail(NRR_ERR_UNSUPPORTED, "volume too large");
-    const nrr::StatsLayout L = nrr::stats_layout(dtype, dims, block, false);
-    if (workspace_bytes < L.total)
+    *L = nrr::stats_layout(dtype, dims, block, false);
+    if (workspace_bytes < L->total)
         return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
-                    L.total);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = nrr::launch_stats(flt, dtype, dims, block, false, workspace, st);
-    if (e != hipSuccess) return hip_status(e, "window statistics launch");
+                    L->total);
+    return NRR_OK;
+}
+
+nrr_status run_aniso(const void *ref, const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                     const int32_t *centers, int64_t n, const int32_t block[3],
+                     const int32_t window[3], int32_t *disp, float *ncc, float *conf,
+                     const void *workspace, const nrr::StatsLayout &L, hipStream_t st) {
     nrr::AnisoArgs a;
     a.ref = ref;
     a.flt = flt;
@@ -501,6 +508,55 @@ nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dty
     a.conf = conf;
     a.cz = 0;
     return hip_status(nrr::launch_match_aniso(dtype, a, st), "per-axis search launch");
+}
+
+}  // namespace
+
+nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dtype,
+                                 const int32_t dims[3], const int32_t *centers, int64_t n,
+                                 const int32_t block[3], const int32_t window[3], int32_t *disp,
+                                 float *ncc, float *conf, void *workspace, size_t workspace_bytes,
+                                 void *stream) {
+    nrr::StatsLayout L;
+    nrr_status s = check_aniso(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf,
+                               workspace, workspace_bytes, &L);
+    if (s != NRR_OK || n == 0) return s == NRR_OK ? ok() : s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = nrr::launch_stats(flt, dtype, dims, block, false, workspace, st);
+    if (e != hipSuccess) return hip_status(e, "window statistics launch");
+    return run_aniso(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf, workspace,
+                     L, st);
+}
+
+nrr_status nrr_window_stats_aniso(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                                  const int32_t block[3], void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    nrr::BoxGrid G;
+    if ((s = check_box(dims, block, nullptr, &G)) != NRR_OK) return s;
+    if (!flt || !workspace) return fail(NRR_ERR_INVALID_ARG, "flt and workspace must be non-NULL");
+    const nrr::StatsLayout L = nrr::stats_layout(dtype, dims, block, false);
+    if (workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
+                    L.total);
+    return hip_status(nrr::launch_stats(flt, dtype, dims, block, false, workspace,
+                                        static_cast<hipStream_t>(stream)),
+                      "window statistics launch");
+}
+
+nrr_status nrr_block_match_aniso_prepared(const void *ref, const void *flt, nrr_dtype dtype,
+                                          const int32_t dims[3], const int32_t *centers,
+                                          int64_t n, const int32_t block[3],
+                                          const int32_t window[3], int32_t *disp, float *ncc,
+                                          float *conf, const void *workspace,
+                                          size_t workspace_bytes, void *stream) {
+    nrr::StatsLayout L;
+    nrr_status s = check_aniso(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf,
+                               workspace, workspace_bytes, &L);
+    if (s != NRR_OK || n == 0) return s == NRR_OK ? ok() : s;
+    return run_aniso(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf, workspace,
+                     L, static_cast<hipStream_t>(stream));
 }
 
 nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int32_t dims[3],

@@ -136,7 +136,7 @@ struct AnisoArgs {
     int32_t *disp;
     float *ncc;
     float *conf;
-    int32_t cz;
+    int32_t cz;  // displacement planes per LDS run
 };
 const char *aniso_unsupported_reason(const int32_t block[3], const int32_t window[3]);
 hipError_t launch_match_aniso(nrr_dtype dtype, const AnisoArgs &a, hipStream_t stream);

@@ -153,3 +153,17 @@ def test_mri_sized_case(torch_dev):
     sample = np.arange(0, len(want), max(1, len(want) // 150))
     check_aniso(p.ref, p.flt, want[sample], b, w, to_host(d)[sample], to_host(n)[sample],
                 to_host(cf)[sample], "mri")
+
+
+def test_prepared_statistics_give_the_same_results(torch_dev):
+    p = synth.gen_random(73, (30, 26, 22), "u16", smooth=1.0)
+    r, f = to_dev(p.ref), to_dev(p.flt)
+    b, s, w = (5, 7, 3), (5, 7, 3), (3, 2, 2)
+    c = nrr.select_blocks_aniso(r, b, s, 0.5)
+    say("aniso prepared", c.shape[0])
+    d1, n1, c1 = nrr.block_match_aniso(r, f, c, b, w)
+    ws = nrr.window_stats_aniso(f, b)
+    d2, n2, c2 = nrr.block_match_aniso(r, f, c, b, w, workspace=ws, prepared=True)
+    torch_dev.cuda.synchronize()
+    assert np.array_equal(to_host(d1), to_host(d2))
+    assert np.array_equal(to_host(n1), to_host(n2)) and np.array_equal(to_host(c1), to_host(c2))
