@@ -3,8 +3,8 @@
 
 One step = one pass of the whole hot path over one volume pair already
 resident in HBM: variance-ranked selection of the blocks of `ref`, the
-per-voxel window statistics of `flt`, and the exhaustive NCC search of every
-selected block.  The default workload is the MRI-shaped pair (256x256x124
+per-voxel window statistics of `flt` (the two are independent and run on two
+streams), and the exhaustive NCC search of every selected block.  The default workload is the MRI-shaped pair (256x256x124
 uint16, 12-bit, blocks 7^3 on a stride-7 grid, top 25% by variance = 5508
 blocks, window +-10).
 
@@ -48,17 +48,24 @@ PEAK_TOPS = 157.3
 OPS_PER_PAIR = 2  # one multiply-add per (block voxel, displacement) pair
 
 
-# HBM traffic of the search kernel, measured with rocprofv3 counters and kept
-# in profiles/; reported only while the kernel's sources are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_match_u16_mri_256x256x124_traffic.json")
-KERNEL_SOURCES = ["paper_2308_10868_amd/csrc/match.hip", "paper_2308_10868_amd/csrc/nrr_internal.h"]
+# HBM traffic of the search kernels, measured with rocprofv3 counters and kept
+# in profiles/ (one summary per workload); reported only while the kernel's
+# sources are unchanged.
+TRAFFIC_FILES = {
+    "mri_256x256x124_u16": ("k_match_u16_mri_256x256x124_traffic.json",
+                            ["paper_2308_10868_amd/csrc/match.hip",
+                             "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    "mri_aniso_256x256x124_u16": ("k_match_aniso_u16_mri_256x256x124_traffic.json",
+                                  ["paper_2308_10868_amd/csrc/match_aniso.hip",
+                                   "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -66,13 +73,16 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(workload: str):
     """Bytes per search launch from the committed counter summary, or None
-    when it was taken on other sources or another workload."""
+    when it was taken on other sources or there is none for the workload."""
+    if workload not in TRAFFIC_FILES:
+        return None
+    name, sources = TRAFFIC_FILES[workload]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("workload") != workload or t.get("source_sha256") != kernel_source_hash():
+    if t.get("workload") != workload or t.get("source_sha256") != kernel_source_hash(sources):
         return None
     return t.get("traffic_bytes")
 
@@ -199,10 +209,17 @@ def main() -> int:
     ncc = torch.empty(k, dtype=torch.float32, device=dev)
     conf = torch.empty(k, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    side = torch.cuda.Stream(dev)  # default priority
 
     def step(ev_a=None, ev_b=None):
+        # selection (reads ref) and the window statistics (read flt) are
+        # independent: the statistics run on a second stream, after the
+        # previous step's search has released the table
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            nrr.window_stats(flt, b, workspace=mat_ws)
         centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
-        nrr.window_stats(flt, b, workspace=mat_ws)
+        stream.wait_stream(side)
         if ev_a is not None:
             ev_a.record(stream)
         nrr.block_match(ref, flt, centers, b, w, workspace=mat_ws, out=(disp, ncc, conf),
@@ -434,7 +451,8 @@ def bench_aniso(args) -> int:
                    "blocks": int(len(centers_h)), "evaluated_pairs": pairs, "seed": args.seed},
         "search_kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_TOPS, "traffic": None, "kernel": "k_match_aniso"},
+                     "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(ANISO),
+                     "kernel": "k_match_aniso"},
     }
     if args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(pair, centers_h, b, w, args.cpu_budget)
