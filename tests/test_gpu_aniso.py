@@ -167,3 +167,52 @@ def test_prepared_statistics_give_the_same_results(torch_dev):
     torch_dev.cuda.synchronize()
     assert np.array_equal(to_host(d1), to_host(d2))
     assert np.array_equal(to_host(n1), to_host(n2)) and np.array_equal(to_host(c1), to_host(c2))
+
+
+def test_full_size_bench_configuration_sampled(torch_dev):
+    """The per-axis workload the benchmark times (256 x 256 x 124 MRI pair,
+    blocks 7 x 7 x 3 on a (7, 7, 3) grid, F = 0.25, half windows (10, 10, 4)),
+    in the same launch: the selection compared whole, the search on every
+    40th block plus the blocks nearest the volume's faces."""
+    import torch
+
+    from bench import ANISO_CFG
+
+    p = synth.gen_mri_u16(seed=0)
+    b, s, f, w = (ANISO_CFG[k] for k in ("block", "stride", "fraction", "window"))
+    r, fl = to_dev(p.ref), to_dev(p.flt)
+    c = nrr.select_blocks_aniso(r, b, s, f)
+    d, n, cf = nrr.block_match_aniso(r, fl, c, b, w)
+    torch.cuda.synchronize()
+    want, _ = oracle.select_aniso(p.ref, b, s, f)
+    say("aniso full size", len(want))
+    assert np.array_equal(to_host(c), want)
+    lo = want.min(axis=0)
+    hi = want.max(axis=0)
+    edge = np.flatnonzero(np.any((want == lo) | (want == hi), axis=1))[::7]
+    sample = np.unique(np.concatenate([np.arange(0, len(want), 40), edge]))
+    check_aniso(p.ref, p.flt, want[sample], b, w, to_host(d)[sample], to_host(n)[sample],
+                to_host(cf)[sample], "full size")
+
+
+@pytest.mark.parametrize("b,s,w", SHAPES[:4])
+def test_dot2_form_parity(torch_dev, monkeypatch, b, s, w):
+    """The DOT2 form for 12-bit data (selected by NRR_ANISO_ARITH=dot2) under
+    the same parity rule, with border and outside blocks."""
+    monkeypatch.setenv("NRR_ANISO_ARITH", "dot2")
+    p = synth.gen_random(74, (23, 19, 17), "u16", smooth=1.0)
+    cen, _ = oracle.select_aniso(p.ref, b, s, 0.5)
+    h = [(v - 1) // 2 for v in b]
+    extra = np.array([[h[0], h[1], h[2]], [22 - h[0], 18 - h[1], 16 - h[2]], [22, 18, 16]],
+                     np.int32)
+    cen = np.concatenate([cen, extra]).astype(np.int32)
+    say("aniso dot2", b, w, len(cen))
+    dg, ng, cg = run(torch_dev, p.ref, p.flt, cen, b, w)
+    check_aniso(p.ref, p.flt, cen, b, w, dg, ng, cg, ("dot2", b, w))
+    # a checkerboard of 0 and 4095: the largest exact int32 plane sums
+    q = np.indices((17, 17, 17)).sum(axis=0) % 2 * 4095
+    ref = q.astype(np.uint16)
+    flt = np.roll(ref, 1, axis=2)
+    c = np.array([[8, 8, 8]], np.int32)
+    dg, ng, cg = run(torch_dev, ref, flt, c, (15, 15, 15), (1, 1, 1))
+    check_aniso(ref, flt, c, (15, 15, 15), (1, 1, 1), dg, ng, cg, "checkerboard")
