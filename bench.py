@@ -121,27 +121,37 @@ def to_dev(a: np.ndarray, torch):
 
 def cpu_baseline(pair, centers: np.ndarray, b, w, budget_s: float):
     """Time the FP64 oracle on a bounded, seeded sample of the selected blocks
-    (per-axis search when b is a triple)."""
+    (per-axis search when b is a triple): on all host threads with about
+    two thirds of the budget, then on one thread with the rest."""
     import oracle
 
     oracle.build()
     search = oracle.match if np.ndim(b) == 0 else oracle.match_aniso
     rng = np.random.default_rng(1)
     order = rng.permutation(len(centers))
-    probe = centers[order[:32]]
-    t = time.perf_counter()
-    search(pair.ref, pair.flt, probe, b, w)
-    dt = max(time.perf_counter() - t, 1e-6)
-    per_block = dt / len(probe)
-    n = int(min(len(centers), max(32, budget_s / per_block)))
-    sample = centers[order[:n]]
-    t = time.perf_counter()
-    search(pair.ref, pair.flt, sample, b, w)
-    dt = time.perf_counter() - t
-    pairs = evaluated_pairs(sample, pair.dims, b, w)
-    return {"value": pairs / dt, "unit": "voxel-pairs/s", "cores": oracle.threads(),
-            "kind": "oracle", "sample": "%d of %d selected blocks (seeded), %.3g pairs, %.1f s"
-            % (n, len(centers), pairs, dt)}
+
+    def timed(n_probe, budget):
+        probe = centers[order[:n_probe]]
+        t = time.perf_counter()
+        search(pair.ref, pair.flt, probe, b, w)
+        per_block = max(time.perf_counter() - t, 1e-6) / len(probe)
+        n = int(min(len(centers), max(n_probe, budget / per_block)))
+        sample = centers[order[:n]]
+        t = time.perf_counter()
+        search(pair.ref, pair.flt, sample, b, w)
+        dt = time.perf_counter() - t
+        return evaluated_pairs(sample, pair.dims, b, w), dt, n
+
+    cores = oracle.threads()
+    pairs, dt, n = timed(32, budget_s * 2 / 3)
+    oracle.set_threads(1)
+    pairs1, dt1, n1 = timed(4, budget_s / 3)
+    oracle.set_threads(cores)
+    return {"value": pairs / dt, "unit": "voxel-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d selected blocks (seeded), %.3g pairs, %.1f s"
+            % (n, len(centers), pairs, dt),
+            "value_1core": pairs1 / dt1,
+            "sample_1core": "%d blocks, %.3g pairs, %.1f s" % (n1, pairs1, dt1)}
 
 
 def main() -> int:
@@ -211,21 +221,26 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     side = torch.cuda.Stream(dev)  # default priority
 
-    def step(ev_a=None, ev_b=None):
+    def step(ev=None):
         # selection (reads ref) and the window statistics (read flt) are
         # independent: the statistics run on a second stream, after the
-        # previous step's search has released the table
+        # previous step's search has released the table.  ev: events around
+        # the selection and around the search, all on the main stream.
         side.wait_stream(stream)
         with torch.cuda.stream(side):
             nrr.window_stats(flt, b, workspace=mat_ws)
+        if ev is not None:
+            ev[0].record(stream)
         centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
+        if ev is not None:
+            ev[1].record(stream)
         stream.wait_stream(side)
-        if ev_a is not None:
-            ev_a.record(stream)
+        if ev is not None:
+            ev[2].record(stream)
         nrr.block_match(ref, flt, centers, b, w, workspace=mat_ws, out=(disp, ncc, conf),
                         prepared=True)
-        if ev_b is not None:
-            ev_b.record(stream)
+        if ev is not None:
+            ev[3].record(stream)
         return centers
 
     for _ in range(args.warmup):
@@ -235,16 +250,18 @@ def main() -> int:
     pairs = evaluated_pairs(centers_h, dims, b, w)
     nominal = k * b ** 3 * (2 * w + 1) ** 3
 
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    evs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for ea, eb in evs:
-        step(ea, eb)
+    for ev in evs:
+        step(ev)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t
     ms_step = elapsed * 1e3 / args.steps
-    kern_ms = float(np.mean([ea.elapsed_time(eb) for ea, eb in evs]))
+    search_ms = np.array([ev[2].elapsed_time(ev[3]) for ev in evs])
+    select_ms = np.array([ev[0].elapsed_time(ev[1]) for ev in evs])
+    kern_ms = float(np.mean(search_ms))
 
     lat = []
     for _ in range(args.latency_reps):
@@ -276,7 +293,11 @@ def main() -> int:
                        "reps": args.latency_reps,
                        "what": "select_blocks + block_match, enqueue to stream sync"},
         "search_kernel_ms": kern_ms,
+        "search_kernel_ms_median": float(np.median(search_ms)),
         "search_pairs_per_s": pairs / (kern_ms * 1e-3),
+        "selection_ms": {"mean": float(np.mean(select_ms)), "median": float(np.median(select_ms)),
+                         "what": "select_blocks on the main stream, beside the window "
+                                 "statistics on the second"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_match_u16" if dt_code == nrr.U16 else "k_match_f32"},

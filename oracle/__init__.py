@@ -70,6 +70,8 @@ def _load():
         lib.oracle_match_aniso.argtypes = [P, P, ctypes.c_int, P, P, i64, P, P, P, P, P]
         lib.oracle_ncc_aniso_at.restype = ctypes.c_int
         lib.oracle_ncc_aniso_at.argtypes = [P, P, ctypes.c_int, P, P, P, i64, P, P]
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -91,6 +93,11 @@ def _dims(a: np.ndarray) -> np.ndarray:
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    """Cap the OpenMP threads of later oracle calls in this process."""
+    _load().oracle_set_threads(int(n))
 
 
 def threads() -> int:

@@ -695,6 +695,16 @@ int oracle_ncc_aniso_at(const void *ref, const void *flt, int dtype, const int32
     return 0;
 }
 
+/* Cap the OpenMP threads of later oracle calls (timing on one core). */
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_threads(void) {
 #ifdef _OPENMP
     extern int omp_get_max_threads(void);
