@@ -883,17 +883,23 @@ struct Variant {
 #define V32F(B, RX, RY, NT, PF) \
     {NRR_F32, FMA, B, RX, RY, NT, PF, k_match<float, FMA, B, RX, RY, NT, PF>}
 
-// Order matters only between equal-cost shapes (the first wins).
+// Order matters only between equal-cost shapes (the first wins).  The cost
+// model counts wavefront rounds, not occupancy, so shapes that lose on
+// occupancy are left out rather than modelled: FMA 3x7 tiles at 448 threads
+// (b = 7) ran 1.7x slower than at 256 on the 256x256x124 volume (W = 10) and
+// 2.5x slower at W = 5.
 const Variant kVariants[] = {
     V16D(3, 4, 4, 256, 0),  V16D(5, 4, 4, 256, 0),  V16D(5, 3, 7, 448, 0),
     V16D(7, 3, 7, 256, 1),  V16D(7, 3, 7, 256, 0),  V16D(7, 4, 4, 256, 0),
     V16D(7, 3, 5, 256, 0),  V16D(7, 5, 5, 256, 0),  V16D(9, 4, 4, 256, 0),
     V16D(9, 5, 5, 256, 0),  V16D(11, 3, 3, 256, 0), V16D(13, 3, 3, 256, 0),
     V16D(15, 2, 2, 256, 0), V16F(3, 4, 4, 256, 0),  V16F(5, 4, 4, 256, 0),
-    V16F(5, 3, 7, 448, 0),  V16F(7, 4, 4, 256, 0),  V16F(7, 3, 7, 448, 0),
+    V16F(5, 3, 7, 448, 0),  V16F(7, 4, 4, 256, 0),  V16F(7, 5, 5, 256, 0),
+    V16F(7, 3, 7, 256, 0),
     V16F(9, 4, 4, 256, 0),  V16F(9, 5, 5, 256, 0),  V16F(11, 3, 3, 256, 0),
     V16F(13, 3, 3, 256, 0), V16F(15, 2, 2, 256, 0), V32F(3, 4, 4, 256, 0),
-    V32F(5, 4, 4, 256, 0),  V32F(7, 4, 4, 256, 0),  V32F(7, 3, 7, 448, 0),
+    V32F(5, 4, 4, 256, 0),  V32F(7, 4, 4, 256, 0),  V32F(7, 5, 5, 256, 0),
+    V32F(7, 3, 7, 256, 0),  V32F(9, 5, 5, 256, 0),
     V32F(9, 4, 4, 256, 0),  V32F(11, 3, 3, 256, 0), V32F(13, 3, 3, 256, 0),
     V32F(15, 2, 2, 256, 0),
 };
