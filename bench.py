@@ -4,7 +4,8 @@
 One step = one pass of the whole hot path over one volume pair already
 resident in HBM: variance-ranked selection of the blocks of `ref`, the
 per-voxel window statistics of `flt` (the two are independent and run on two
-streams), and the exhaustive NCC search of every selected block.  The default workload is the MRI-shaped pair (256x256x124
+streams; their launches are captured once as a HIP graph and replayed), and
+the exhaustive NCC search of every selected block.  The default workload is the MRI-shaped pair (256x256x124
 uint16, 12-bit, blocks 7^3 on a stride-7 grid, top 25% by variance = 5508
 blocks, window +-10).
 
@@ -170,6 +171,8 @@ def main() -> int:
                     help="only run a 256 MiB device-to-device copy 3 times (the reference "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch the selection and statistics eagerly every step")
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 = skip)")
@@ -265,6 +268,50 @@ def main() -> int:
     search_ms = np.array([ev[2].elapsed_time(ev[3]) for ev in evs])
     select_ms = np.array([ev[0].elapsed_time(ev[1]) for ev in evs])
     kern_ms = float(np.mean(search_ms))
+    eager = {"ms_per_step": ms_step, "value": pairs / (ms_step * 1e-3)}
+
+    graph = None
+    if not args.no_graph:
+        # the launches before the search (selection on this stream, window
+        # statistics on the second) captured once as a HIP graph and replayed
+        # each step; the search stays a plain launch between HIP events
+        ref_disp = disp.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            cap = torch.cuda.current_stream()
+            side.wait_stream(cap)
+            with torch.cuda.stream(side):
+                nrr.window_stats(flt, b, workspace=mat_ws)
+            g_centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
+            cap.wait_stream(side)
+        torch.cuda.synchronize()
+
+        def gstep(ev=None):
+            g.replay()
+            if ev is not None:
+                ev[2].record(stream)
+            nrr.block_match(ref, flt, g_centers, b, w, workspace=mat_ws, out=(disp, ncc, conf),
+                            prepared=True)
+            if ev is not None:
+                ev[3].record(stream)
+
+        for _ in range(args.warmup):
+            gstep()
+        torch.cuda.synchronize()
+        # a replay must give the eager results
+        assert torch.equal(g_centers.cpu(), centers.cpu()), "graph replay: selection differs"
+        assert torch.equal(disp, ref_disp), "graph replay: displacements differ"
+        gevs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
+                for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for ev in gevs:
+            gstep(ev)
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t) * 1e3 / args.steps
+        search_ms = np.array([ev[2].elapsed_time(ev[3]) for ev in gevs])
+        kern_ms = float(np.mean(search_ms))
+        graph = True
 
     lat = []
     for _ in range(args.latency_reps):
@@ -295,12 +342,15 @@ def main() -> int:
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "reps": args.latency_reps,
                        "what": "select_blocks + block_match, enqueue to stream sync"},
+        "step_launch": "graph (selection + statistics captured once) + search launch"
+                       if graph else "eager",
+        "eager_step": eager,
         "search_kernel_ms": kern_ms,
         "search_kernel_ms_median": float(np.median(search_ms)),
         "search_pairs_per_s": pairs / (kern_ms * 1e-3),
         "selection_ms": {"mean": float(np.mean(select_ms)), "median": float(np.median(select_ms)),
                          "what": "select_blocks on the main stream, beside the window "
-                                 "statistics on the second"},
+                                 "statistics on the second (eager steps)"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_match_u16" if dt_code == nrr.U16 else "k_match_f32"},
