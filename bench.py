@@ -270,48 +270,53 @@ def main() -> int:
     kern_ms = float(np.mean(search_ms))
     eager = {"ms_per_step": ms_step, "value": pairs / (ms_step * 1e-3)}
 
-    graph = None
+    graph, graph_error = None, None
     if not args.no_graph:
         # the launches before the search (selection on this stream, window
         # statistics on the second) captured once as a HIP graph and replayed
-        # each step; the search stays a plain launch between HIP events
-        ref_disp = disp.clone()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            cap = torch.cuda.current_stream()
-            side.wait_stream(cap)
-            with torch.cuda.stream(side):
-                nrr.window_stats(flt, b, workspace=mat_ws)
-            g_centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
-            cap.wait_stream(side)
-        torch.cuda.synchronize()
+        # each step; the search stays a plain launch between HIP events.  If
+        # capture fails, or a replay differs from the eager step, the eager
+        # timing above stands and the reason is reported.
+        try:
+            ref_disp = disp.clone()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                cap = torch.cuda.current_stream()
+                side.wait_stream(cap)
+                with torch.cuda.stream(side):
+                    nrr.window_stats(flt, b, workspace=mat_ws)
+                g_centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
+                cap.wait_stream(side)
+            torch.cuda.synchronize()
 
-        def gstep(ev=None):
-            g.replay()
-            if ev is not None:
-                ev[2].record(stream)
-            nrr.block_match(ref, flt, g_centers, b, w, workspace=mat_ws, out=(disp, ncc, conf),
-                            prepared=True)
-            if ev is not None:
-                ev[3].record(stream)
+            def gstep(ev=None):
+                g.replay()
+                if ev is not None:
+                    ev[2].record(stream)
+                nrr.block_match(ref, flt, g_centers, b, w, workspace=mat_ws,
+                                out=(disp, ncc, conf), prepared=True)
+                if ev is not None:
+                    ev[3].record(stream)
 
-        for _ in range(args.warmup):
-            gstep()
-        torch.cuda.synchronize()
-        # a replay must give the eager results
-        assert torch.equal(g_centers.cpu(), centers.cpu()), "graph replay: selection differs"
-        assert torch.equal(disp, ref_disp), "graph replay: displacements differ"
-        gevs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
-                for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for ev in gevs:
-            gstep(ev)
-        torch.cuda.synchronize()
-        ms_step = (time.perf_counter() - t) * 1e3 / args.steps
-        search_ms = np.array([ev[2].elapsed_time(ev[3]) for ev in gevs])
-        kern_ms = float(np.mean(search_ms))
-        graph = True
+            for _ in range(args.warmup):
+                gstep()
+            torch.cuda.synchronize()
+            if not (torch.equal(g_centers.cpu(), centers.cpu()) and torch.equal(disp, ref_disp)):
+                raise RuntimeError("a graph replay differs from the eager step")
+            gevs = [tuple(torch.cuda.Event(enable_timing=True) for _ in range(4))
+                    for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for ev in gevs:
+                gstep(ev)
+            torch.cuda.synchronize()
+            g_ms = (time.perf_counter() - t) * 1e3 / args.steps
+            g_search = np.array([ev[2].elapsed_time(ev[3]) for ev in gevs])
+            ms_step, search_ms, kern_ms = g_ms, g_search, float(np.mean(g_search))
+            graph = True
+        except Exception as e:  # noqa: BLE001 - reported in the JSON line
+            graph_error = "%s: %s" % (type(e).__name__, e)
+            torch.cuda.synchronize()
 
     lat = []
     for _ in range(args.latency_reps):
@@ -344,6 +349,7 @@ def main() -> int:
                        "what": "select_blocks + block_match, enqueue to stream sync"},
         "step_launch": "graph (selection + statistics captured once) + search launch"
                        if graph else "eager",
+        "graph_error": graph_error,
         "eager_step": eager,
         "search_kernel_ms": kern_ms,
         "search_kernel_ms_median": float(np.median(search_ms)),
