@@ -115,14 +115,21 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
                                                            SelectState *__restrict__ st) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int64_t s_need;
+    __shared__ int64_t s_need, s_bucket;
     __shared__ uint64_t s_or;
+    // once the bucket holding the K-th key fits, its keys move to LDS and the
+    // remaining digit passes read them there instead of the whole key array
+    constexpr int CAP = 6144;
+    __shared__ uint64_t lk[CAP];
+    __shared__ int s_fill;
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_prefix = 0;
         s_mask = 0;
         s_need = k;
         s_or = 0;
+        s_bucket = n;
+        s_fill = 0;
     }
     __syncthreads();
     // skip leading bytes that are zero in every key
@@ -138,23 +145,25 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
     __syncthreads();
     int top = 56;
     while (top > 0 && ((s_or >> top) & 0xff) == 0) top -= 8;
+    bool local = false;  // keys read from lk (uniform)
+    int64_t cnt = n;
     for (int shift = top; shift >= 0; shift -= 8) {
         for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix, mask = s_mask;
         constexpr int UNR = 8;  // keys loaded per thread before any is counted
-        const int64_t iters = (n + blockDim.x - 1) / blockDim.x;
+        const int64_t iters = (cnt + blockDim.x - 1) / blockDim.x;
         for (int64_t it = 0; it < iters; it += UNR) {  // uniform trip count: ballots converge
             uint64_t kv[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = (it + u) * blockDim.x + tid;
-                kv[u] = i < n ? keys[i] : 0;
+                kv[u] = i < cnt ? (local ? lk[i] : keys[i]) : 0;
             }
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 const int64_t i = (it + u) * blockDim.x + tid;
-                const bool valid = i < n && (kv[u] & mask) == prefix;
+                const bool valid = i < cnt && (kv[u] & mask) == prefix;
                 hist_add(hist, (uint32_t)((kv[u] >> shift) & 0xff), valid);
             }
         }
@@ -185,6 +194,7 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
                         s_need = need - cum;
                         s_prefix = prefix | ((uint64_t)d << shift);
                         s_mask = mask | (0xffull << shift);
+                        s_bucket = h4[j];
                         break;
                     }
                     cum += h4[j];
@@ -192,6 +202,17 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
             }
         }
         __syncthreads();
+        if (!local && shift > 0 && s_bucket <= CAP) {
+            // copy the keys of the chosen bucket (in any order) into LDS
+            const uint64_t p2 = s_prefix, m2 = s_mask;
+            for (int64_t i = tid; i < n; i += blockDim.x) {
+                const uint64_t kv = keys[i];
+                if ((kv & m2) == p2) lk[atomicAdd(&s_fill, 1)] = kv;
+            }
+            __syncthreads();
+            local = true;
+            cnt = s_fill;  // == s_bucket
+        }
     }
     if (tid == 0) {
         // bytes below `top`+8 were all resolved; bytes above are zero in every key
