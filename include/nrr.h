@@ -57,7 +57,7 @@ typedef enum {
     NRR_ERR_INVALID_ARG = 1,      /* bad size, null pointer, out-of-range parameter */
     NRR_ERR_BUFFER_TOO_SMALL = 2, /* output capacity or workspace too small */
     NRR_ERR_HIP = 3,              /* a HIP runtime call or kernel launch failed */
-    NRR_ERR_UNSUPPORTED = 4       /* valid request outside this build's limits */
+    NRR_ERR_UNSUPPORTED = 4       /* valid request outside the compiled limits */
 } nrr_status;
 
 typedef enum {
