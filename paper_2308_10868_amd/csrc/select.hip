@@ -396,11 +396,17 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
     __shared__ uint32_t hist[2048];
     __shared__ int64_t s_w[16];
     __shared__ int s_changed;
+    __shared__ int32_t s_off[26];  // grid-index offset of neighbour j
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_need;
     const int tid = threadIdx.x;
     // neighbours of the pattern: one, up to two, or up to three axis steps
     const int max_steps = connectivity == 6 ? 1 : (connectivity == 18 ? 2 : (connectivity == 26 ? 3 : 0));
+    if (tid < 26) {
+        int dx, dy, dz;
+        nb_offset(tid, &dx, &dy, &dz);
+        s_off[tid] = (dz * gy + dy) * gx + dx;
+    }
     int64_t in_local = 0;
     for (int64_t g = tid; g < n; g += 1024) {
         const int ix = (int)(g % gx), iy = (int)((g / gx) % gy), iz = (int)(g / ((int64_t)gx * gy));
@@ -433,18 +439,14 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
         if (tid == 0) s_changed = 0;
         __syncthreads();
         int changed = 0;
-        for (int64_t g = tid; g < n; g += 1024) {
+        for (int g = tid; g < (int)n; g += 1024) {  // n <= kExCand
             if (state[g] != 0) continue;
-            const int ix = (int)(g % gx), iy = (int)((g / gx) % gy), iz = (int)(g / ((int64_t)gx * gy));
             bool any_taken = false, all_out = true;
-            uint32_t bits = above[g];
+            uint32_t bits = above[g];  // only neighbours inside the grid are flagged
             while (bits) {
                 const int j = __ffs(bits) - 1;
                 bits &= bits - 1;
-                int dx, dy, dz;
-                nb_offset(j, &dx, &dy, &dz);
-                const int64_t q = ((int64_t)(iz + dz) * gy + (iy + dy)) * gx + (ix + dx);
-                const uint8_t sq = state[q];
+                const uint8_t sq = state[g + s_off[j]];
                 any_taken |= sq == 1;
                 all_out &= sq >= 2;
             }
