@@ -397,6 +397,8 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
     __shared__ int64_t s_w[16];
     __shared__ int s_changed;
     __shared__ int32_t s_off[26];  // grid-index offset of neighbour j
+    __shared__ int8_t s_dir[26][4];  // the pattern's neighbours: j, dx, dy, dz
+    __shared__ int s_ndir;
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_need;
     const int tid = threadIdx.x;
@@ -407,9 +409,26 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
         nb_offset(tid, &dx, &dy, &dz);
         s_off[tid] = (dz * gy + dy) * gx + dx;
     }
+    if (tid == 0) {  // the neighbours the pattern looks at
+        int c = 0;
+        for (int j = 0; j < 26; ++j) {
+            int dx, dy, dz;
+            nb_offset(j, &dx, &dy, &dz);
+            if ((dx != 0) + (dy != 0) + (dz != 0) > max_steps) continue;
+            s_dir[c][0] = (int8_t)j;
+            s_dir[c][1] = (int8_t)dx;
+            s_dir[c][2] = (int8_t)dy;
+            s_dir[c][3] = (int8_t)dz;
+            ++c;
+        }
+        s_ndir = c;
+    }
+    __syncthreads();
+    const int ndir = s_ndir;
     int64_t in_local = 0;
-    for (int64_t g = tid; g < n; g += 1024) {
-        const int ix = (int)(g % gx), iy = (int)((g / gx) % gy), iz = (int)(g / ((int64_t)gx * gy));
+    const int gxy = gx * gy;
+    for (int g = tid; g < (int)n; g += 1024) {  // n <= kExCand: 32-bit index arithmetic
+        const int iz = g / gxy, r = g - iz * gxy, iy = r / gx, ix = r - iy * gx;
         bool in = true;
         if (mask)
             in = mask[((int64_t)(iz * stride + h) * ny + (iy * stride + h)) * nx + (ix * stride + h)] != 0;
@@ -417,14 +436,11 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
         in_local += in;
         uint32_t bits = 0;
         const uint64_t kg = keys[g];
-        for (int j = 0; j < 26 && max_steps > 0; ++j) {
-            int dx, dy, dz;
-            nb_offset(j, &dx, &dy, &dz);
-            if ((dx != 0) + (dy != 0) + (dz != 0) > max_steps) continue;
-            const int x = ix + dx, y = iy + dy, z = iz + dz;
+        for (int t = 0; t < ndir; ++t) {
+            const int x = ix + s_dir[t][1], y = iy + s_dir[t][2], z = iz + s_dir[t][3];
             if (x < 0 || y < 0 || z < 0 || x >= gx || y >= gy || z >= gz) continue;
-            const int64_t q = ((int64_t)z * gy + y) * gx + x;
-            if (ranks_above(keys[q], q, kg, g)) bits |= 1u << j;
+            const int q = (z * gy + y) * gx + x;
+            if (ranks_above(keys[q], q, kg, g)) bits |= 1u << s_dir[t][0];
         }
         above[g] = bits;
     }
@@ -526,7 +542,8 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
         const bool is_gt = all || kv > kth, is_eq = !all && kv == kth;
         if (is_gt || (is_eq && eq_before < take_eq)) {
             const int64_t pos = gt_before + (eq_before < take_eq ? eq_before : take_eq);
-            const int64_t ix = g % gx, iy = (g / gx) % gy, iz = g / ((int64_t)gx * gy);
+            const int gi = (int)g, iz = gi / (gx * gy), r = gi - iz * gx * gy, iy = r / gx,
+                      ix = r - iy * gx;
             centers[3 * pos + 0] = (int32_t)(ix * stride + h);
             centers[3 * pos + 1] = (int32_t)(iy * stride + h);
             centers[3 * pos + 2] = (int32_t)(iz * stride + h);
