@@ -150,6 +150,9 @@ nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dim
     if (!(fraction > 0.0) || fraction > 1.0)
         return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
     const int64_t n = (int64_t)g[0] * g[1] * g[2];
+    if (n >= (1ll << 31))
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (grids of 2^31 or more are not built)",
+                    (long long)n);
     const int64_t k = count_rule(n, fraction);
     *k_out = k;
     if (capacity < k)
@@ -434,6 +437,9 @@ nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32
     if (!(fraction > 0.0) || fraction > 1.0)
         return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
     const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
+    if (n >= (1ll << 31))
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (grids of 2^31 or more are not built)",
+                    (long long)n);
     const int64_t k = count_rule(n, fraction);
     *k_out = k;
     if (capacity < k)

@@ -34,8 +34,10 @@ __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restri
     const int lane = threadIdx.x & 63;
     if (g >= n) return;  // whole wavefront leaves together
     const int bx = G.b[0], by = G.b[1], bz = G.b[2];
-    const int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1], iz = g / ((int64_t)G.g[0] * G.g[1]);
-    const int64_t x0 = ix * G.s[0], y0 = iy * G.s[1], z0 = iz * G.s[2];
+    // candidate coordinates in 32-bit arithmetic (grids hold < 2^31 candidates)
+    const int gi = (int)g, gxy = G.g[0] * G.g[1];
+    const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
+    const int64_t x0 = (int64_t)ix * G.s[0], y0 = (int64_t)iy * G.s[1], z0 = (int64_t)iz * G.s[2];
     uint64_t s = 0, q = 0;
     for (int r = lane; r < by * bz; r += 64) {
         const int z = r / by, y = r - z * by;
@@ -87,9 +89,10 @@ __global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict_
                                                         uint64_t *__restrict__ keys) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
-    int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1], iz = g / ((int64_t)G.g[0] * G.g[1]);
-    keys[g] = key_f32(vol, nx, ny, G.b[0], G.b[1], G.b[2], ix * G.s[0], iy * G.s[1],
-                      iz * G.s[2]);
+    const int gi = (int)g, gxy = G.g[0] * G.g[1];
+    const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
+    keys[g] = key_f32(vol, nx, ny, G.b[0], G.b[1], G.b[2], (int64_t)ix * G.s[0],
+                      (int64_t)iy * G.s[1], (int64_t)iz * G.s[2]);
 }
 
 // Count `d` (< 256) into the LDS histogram.  A wavefront whose counted lanes
@@ -324,8 +327,8 @@ __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ ke
         bool keep = is_gt || (is_eq && eq_before < take);
         const int64_t pos = gt_before + (eq_before < take ? eq_before : take);
         if (keep && pos < k) {
-            const int64_t ix = g % G.g[0], iy = (g / G.g[0]) % G.g[1],
-                          iz = g / ((int64_t)G.g[0] * G.g[1]);
+            const int gi = (int)g, gxy = G.g[0] * G.g[1];
+            const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
             centers[3 * pos + 0] = (int32_t)(ix * G.s[0] + (G.b[0] - 1) / 2);
             centers[3 * pos + 1] = (int32_t)(iy * G.s[1] + (G.b[1] - 1) / 2);
             centers[3 * pos + 2] = (int32_t)(iz * G.s[2] + (G.b[2] - 1) / 2);

@@ -93,6 +93,7 @@ bool footprint(const nrr_request &r, Footprint *f) {
     int64_t k = 0;
     size_t selb = 0, statsb = 0;
     if (nrr_grid_shape(r.dims, r.block, r.stride, f->grid) != NRR_OK) return false;
+    if ((int64_t)f->grid[0] * f->grid[1] * f->grid[2] >= (1ll << 31)) return false;
     if (nrr_select_count(r.dims, r.block, r.stride, r.fraction, &k) != NRR_OK) return false;
     if (nrr_select_workspace_bytes(r.dims, r.block, r.stride, &selb) != NRR_OK) return false;
     if (nrr_match_workspace_bytes(r.dtype, r.dims, r.block, &statsb) != NRR_OK) return false;
