@@ -109,7 +109,8 @@ nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window);
  * u16 uses the exact integer key N*sum(x^2)-(sum x)^2; f32 uses the FP64
  * two-pass variance summed in z, y, x order.
  * Errors: INVALID_ARG (bad sizes/fraction, null pointers), BUFFER_TOO_SMALL
- * (capacity < K with *k_out = K, or workspace too small), HIP.  K == 0 is a
+ * (capacity < K with *k_out = K, or workspace too small), UNSUPPORTED (block
+ * edge above 15, or a grid of 2^31 candidates or more), HIP.  K == 0 is a
  * valid no-op. */
 nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                              int32_t block, int32_t stride, double fraction, int32_t *centers,
