@@ -227,17 +227,23 @@ __global__ __launch_bounds__(NT) void k_match_aniso(AnisoArgs p) {
         __syncthreads();  // T written / previous run's readers done
         // lanes along x (coalesced rows of flt), zero outside the window
         // region; SU rows per thread in flight before their LDS stores
-        const int rstep = nw * rpw;
+        const int rstep = nw * rpw;  // <= 8 rows: one wrap of y at most per step
         for (int r0 = (tid >> 6) * rpw + sub; r0 < nrow; r0 += SU * rstep) {
             float v[SU];
+            int z = r0 / EY, y = r0 - z * EY;  // (row, plane) of r, advanced per k
 #pragma unroll
             for (int k = 0; k < SU; ++k) {
-                const int r = r0 + k * rstep, y = r % EY, z = r / EY;
+                const int r = r0 + k * rstep;
                 v[k] = r < nrow && xl < EX
                            ? (float)flt[(wz0 + z0 + z) * g.sz + (int64_t)(wy0 + y) * g.sy + wx0 +
                                         xl] -
                                  cf
                            : 0.0f;
+                y += rstep;
+                while (y >= EY) {
+                    y -= EY;
+                    ++z;
+                }
             }
 #pragma unroll
             for (int k = 0; k < SU; ++k) {
