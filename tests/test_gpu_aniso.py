@@ -120,6 +120,29 @@ def test_flat_and_shift_cases(torch_dev):
     assert np.all(ng == 0) and np.all(cg == 0)
 
 
+def test_full_12bit_range_largest_block(torch_dev):
+    """Voxels over the whole 12-bit range (the documented domain of 16-bit
+    volumes) with 15 x 15 x 15 blocks: the integer sums of the winner's NCC
+    at their largest; a flat moving volume gives NCC 0 at the lowest valid
+    shift index."""
+    rng = np.random.default_rng(93)
+    nz, ny, nx = 24, 26, 28
+    ref = rng.integers(0, 4096, size=(nz, ny, nx)).astype(np.uint16)
+    flt = np.roll(ref, (1, -1, 2), axis=(0, 1, 2))
+    flt[::3] = rng.integers(0, 4096, size=flt[::3].shape).astype(np.uint16)
+    b, w = (15, 15, 15), (2, 1, 2)
+    cen = np.array([[7, 7, 7], [13, 12, 11], [20, 18, 16], [9, 16, 12], [19, 8, 10]], np.int32)
+    say("aniso 12-bit range 15^3")
+    dg, ng, cg = run(torch_dev, ref, flt, cen, b, w)
+    check_aniso(ref, flt, cen, b, w, dg, ng, cg, "12-bit range")
+    flat = np.full_like(ref, 4095)
+    say("aniso 12-bit flat")
+    dg, ng, cg = run(torch_dev, ref, flat, cen, b, w)
+    lo = np.maximum(-np.array(w), 7 - cen)
+    assert np.array_equal(dg, lo)
+    assert np.all(ng == 0) and np.all(cg == 0)
+
+
 def test_cubic_sizes_match_the_cubic_search(torch_dev):
     """Equal per-axis sizes: the same displacements as the tuned cubic path
     (both are held to the oracle; on generic data their argmax agree)."""
