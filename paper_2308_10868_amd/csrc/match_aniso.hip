@@ -41,6 +41,10 @@ constexpr int NT = 256;
 constexpr int TU = 8;   // T row padding and inner-product unroll
 constexpr int SU = 16;  // window rows staged per thread per step
 
+// LDS pitch of a staged window row of `fp` words: an odd number of 16-byte
+// groups, so that rows two apart do not land on the same banks.
+__host__ __device__ inline int row_pitch(int fp) { return (fp / 4) % 2 == 0 ? fp + 4 : fp; }
+
 typedef short short2v __attribute__((ext_vector_type(2)));
 
 template <typename K>
@@ -213,7 +217,8 @@ __global__ __launch_bounds__(NT) void k_match_aniso(AnisoArgs p) {
     const float cf = (float)mt;  // level taken off F (T' sums to zero)
 
     const int ntx = (g.ndx + RX - 1) / RX;
-    const int FP = ntx * RX + TP;  // F row pitch (<= 64): the widest tile's reads stay inside
+    const int FP = ntx * RX + TP;  // F row width read (<= 64): the widest tile's reads stay inside
+    const int FS = row_pitch(FP);
     const int EY = g.ndy + by - 1, EX = g.ndx + bx - 1;
     float *F = T + bz * by * TP;
     const int wx0 = g.cx - g.hx + g.lox, wy0 = g.cy - g.hy + g.loy, wz0 = g.cz - g.hz + g.loz;
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_match_aniso(AnisoArgs p) {
 #pragma unroll
             for (int k = 0; k < SU; ++k) {
                 const int r = r0 + k * rstep;
-                if (r < nrow && xl < FP) F[r * FP + xl] = v[k];
+                if (r < nrow && xl < FP) F[r * FS + xl] = v[k];
             }
         }
         __syncthreads();
@@ -270,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_match_aniso(AnisoArgs p) {
             for (int z = 0; z < bz; ++z)
                 for (int y = 0; y < by; ++y) {
                     const float4 *fr = reinterpret_cast<const float4 *>(
-                        F + ((tz + z) * EY + (ty + y)) * FP + tx * RX);
+                        F + ((tz + z) * EY + (ty + y)) * FS + tx * RX);
                     const float4 *tr = reinterpret_cast<const float4 *>(T + (z * by + y) * TP);
                     for (int c = 0; c < TP / TU; ++c) {
                         // 16-byte LDS reads: pitches and tile offsets are multiples of 4
@@ -472,7 +477,7 @@ struct AnisoPlan {
 size_t aniso_lds(const int32_t b[3], const int32_t w[3], int rx, int cz) {
     const int tp = (b[0] + TU - 1) / TU * TU;
     const int ntx = (2 * w[0] + 1 + rx - 1) / rx;
-    const size_t fp = (size_t)ntx * rx + tp, ey = 2 * w[1] + 1 + b[1] - 1;
+    const size_t fp = row_pitch(ntx * rx + tp), ey = 2 * w[1] + 1 + b[1] - 1;
     return 4 * ((size_t)b[2] * b[1] * tp + (size_t)(cz + b[2] - 1) * ey * fp);
 }
 
@@ -487,8 +492,8 @@ int aniso_cz(const int32_t b[3], const int32_t w[3], int rx, size_t budget) {
 // more than a quarter more idle tile slots than RX = 4 does.  The z-run is
 // the longest that lets six workgroups share a CU's LDS (the kernel is
 // latency-bound: more resident blocks beat fewer re-staged planes; on the
-// MRI pair with 7x7x3 blocks 5 planes ran 0.535 ms, the whole window of 9
-// 0.569 ms), else two, else one.  NRR_ANISO_TILE=rx and NRR_ANISO_CZ=n force
+// MRI pair with 7x7x3 blocks and 32-word rows 5 planes ran 0.535 ms, the
+// whole window of 9 0.569 ms), else two, else one.  NRR_ANISO_TILE=rx and NRR_ANISO_CZ=n force
 // the tile and cap the run (for timing sweeps).
 bool aniso_plan(const int32_t b[3], const int32_t w[3], AnisoPlan *out) {
     const size_t lim = device_lds_limit();
