@@ -21,8 +21,13 @@
 // (sliding windows over 4-wide segments) then along y; the per-plane sums of
 // the last bz planes sit in a small LDS ring, and the z sum slides exactly
 // (integers) or is re-added from the ring (floating point).  The next plane's patch is fetched into registers
-// while the current one is summed (double-buffered LDS patch).
+// while the current one is summed (double-buffered LDS patch).  For 12-bit
+// data the same pass writes the plane-pair volume the search reads (one word
+// per voxel from the staged plane and the next one), each voxel by exactly one
+// workgroup.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "nrr_internal.h"
 
@@ -44,20 +49,25 @@ template <bool SLIDE, typename V, typename A, typename AQ, typename AS, typename
 __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int bx,
                                   int by, int bz,
                                   int ox, int oy, int oz, int zc, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
-                                  A *ringP, AQ *ringQ, Conv conv, Emit emit) {
+                                  A *ringP, AQ *ringQ, uint32_t *__restrict__ pairs, Conv conv,
+                                  Emit emit) {
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;  // output (tx, ty)
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
     const int ph = TY + by - 1, pw = TX + bx - 1;
     const int zend = min(z0 + zc + bz - 1, nz);  // input planes [z0, zend)
-    // this thread's patch elements: fixed offsets inside a plane
+    // this thread's patch elements: fixed offsets inside a plane.  pown: the
+    // element's plane-pair word is this workgroup's to write (its own tile,
+    // and the halo on the last tile of an axis, so every voxel has one writer)
     int goff[PER];
-    bool gok[PER];
+    bool gok[PER], pown[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = tid + 256 * k, r = e / pw, c = e - r * pw;
         gok[k] = e < ph * pw && x0 + c < nx && y0 + r < ny;
         goff[k] = r * nx + c;
+        pown[k] = gok[k] && (c < TX || x0 + TX >= ox) && (r < TY || y0 + TY >= oy);
     }
+    const bool lastz = z0 + zc >= oz;  // the last run also owns the planes past its origins
     const int64_t pstride = (int64_t)ny * nx;
     const Src *pbase = flt + (int64_t)y0 * nx + x0;
     auto fetch = [&](V (&reg)[PER], int zi) {
@@ -78,6 +88,21 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
         const int cur = (zi - z0) & 1;
         const V *pc = patch + cur * PATCH;
         fetch(r2, zi + 2);
+        if constexpr (std::is_same<V, int32_t>::value) {
+            // plane-pair words of this plane (r1 holds the next plane: the
+            // caller asks for them only when a block spans two planes or more,
+            // so the next plane of an owned one is always fetched)
+            if (pairs && (zi < z0 + zc || lastz)) {
+                uint32_t *pl = pairs + (pbase - flt) + (int64_t)zi * pstride;
+#pragma unroll
+                for (int k = 0; k < PER; ++k)
+                    if (pown[k]) {
+                        const int hi = zi + 1 < nz ? r1[k] : 0;
+                        pl[goff[k]] = (uint32_t)(uint16_t)pc[tid + 256 * k] |
+                                      (uint32_t)(uint16_t)hi << 16;
+                    }
+            }
+        }
         // sums along x: SEG outputs per segment by a sliding window
         for (int sg = tid; sg < nseg; sg += 256) {
             const int r = sg / (TX / SEG), xs = (sg % (TX / SEG)) * SEG;
@@ -144,7 +169,8 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
 __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ flt, int nx,
                                                    int ny, int nz, int bx, int by, int bz, int ox,
                                                    int oy, int oz, int zc,
-                                                   StatU16 *__restrict__ out) {
+                                                   StatU16 *__restrict__ out,
+                                                   uint32_t *__restrict__ pairs) {
     __shared__ int32_t patch[2 * PATCH + 256];
     __shared__ int32_t rs[PH * TX];
     __shared__ uint32_t rq[PH * TX];
@@ -154,7 +180,7 @@ __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ 
     uint32_t *ringQ = reinterpret_cast<uint32_t *>(dyn_u16 + (size_t)bz * 256 * 4);
     const int64_t n = (int64_t)bx * by * bz;
     stats_body<true, int32_t, int32_t, uint32_t, int32_t, uint64_t>(
-        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, pairs,
         [](uint16_t v) { return (int32_t)v - 2048; },
         [&](int64_t o, int32_t S, uint64_t QQ) {
             const int64_t var = n * (int64_t)QQ - (int64_t)S * S;
@@ -177,7 +203,7 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
     double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)bz * 256 * 8);
     const double n = (double)bx * by * bz;
     stats_body<false, float, double, double, double, double>(
-        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, nullptr,
         [](float v) { return v; },
         [&](int64_t o, double S, double QQ) {
             const double nq = n * QQ;
@@ -192,6 +218,8 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
 // Plane-pair copy of a 12-bit volume: one 4-byte word per voxel holding the
 // voxel and the one a plane above, both offset by -2048 into int16 (the next
 // plane's half is 0 on the last plane).  Four consecutive voxels per thread.
+// The statistics kernel writes the same words as it goes; this kernel serves
+// blocks one plane thick.
 __global__ __launch_bounds__(256) void k_pair_volume(const uint16_t *__restrict__ flt,
                                                      int64_t nvox, int64_t pstride,
                                                      uint32_t *__restrict__ out) {
@@ -327,10 +355,12 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
     if (dtype == NRR_U16) {
+        uint32_t *pairs =
+            L.pair_off && bz >= 2 ? reinterpret_cast<uint32_t *>(ws + L.pair_off) : nullptr;
         hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)bz * 256 * 8, stream,
                            static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], bx, by,
-                           bz, L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws));
-        if (L.pair_off) {
+                           bz, L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws), pairs);
+        if (L.pair_off && !pairs) {
             const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
             const int64_t groups = (nvox + 1023) / 1024;
             hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
