@@ -353,6 +353,11 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     const int64_t slabs = (512 + per_slab - 1) / per_slab;
     int zc = (int)((L.oz + slabs - 1) / slabs);
     zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
+    // the same number of runs, of balanced lengths: a workgroup's time is
+    // its run plus bz - 1 planes (256x256x124 at b = 7: 30+30+30+28 instead
+    // of 32+32+32+22)
+    const int runs = (L.oz + zc - 1) / zc;
+    zc = (L.oz + runs - 1) / runs;
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
     if (dtype == NRR_U16) {
         uint32_t *pairs =
