@@ -74,8 +74,8 @@ typedef enum {
 nrr_status nrr_grid_shape(const int32_t dims[3], int32_t block, int32_t stride, int32_t grid[3]);
 
 /* Number of blocks the selection keeps: K = floor(0.5 + N * fraction) with
- * N = grid[0]*grid[1]*grid[2] (the count rule "0.5 + NFeatures x Fs" of the
- * parallel feature selection paragraph).  INVALID_ARG as nrr_grid_shape, or
+ * N = grid[0]*grid[1]*grid[2] (the candidate count times the fraction plus
+ * one half, the count rule of the parallel feature selection paragraph).  INVALID_ARG as nrr_grid_shape, or
  * fraction outside (0, 1]. */
 nrr_status nrr_select_count(const int32_t dims[3], int32_t block, int32_t stride, double fraction,
                             int64_t *k);
