@@ -11,7 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnrr.so")
-SOURCES = ["api.cpp", "server.cpp", "select.hip", "stats.hip", "match.hip", "match_aniso.hip"]
+SOURCES = ["api.cpp", "server.cpp", "select.hip", "stats.hip", "match.hip", "match_aniso.hip",
+           "match_mfma.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -982,6 +982,7 @@ int arith_preference() {
     if (!e) return -1;
     if (!strcmp(e, "dot2")) return DOT2;
     if (!strcmp(e, "fma")) return FMA;
+    if (!strcmp(e, "mfma")) return kArithMfma;
     return -1;
 }
 
@@ -1048,6 +1049,7 @@ bool choose(nrr_dtype dtype, int b, int w, size_t limit, const TileShape *force,
     if (!force && shape_from_env(&sh)) force = &sh;
     if (!force && tuned_shape(dtype, b, w, &sh)) force = &sh;
     int pref = arith_preference();
+    if (pref == kArithMfma) pref = -1;  // the matrix-core form does not serve this case
     if (pref < 0 && dtype == NRR_U16 && !(force && force->arith >= 0)) pref = DOT2;
     if (pref >= 0 && choose_with(dtype, b, w, limit, pref, force, best)) return true;
     return choose_with(dtype, b, w, limit, -1, force, best);
@@ -1178,10 +1180,28 @@ void clear_tuned_shapes() {
     g_tuned.clear();
 }
 
+// The matrix-core form serves a launch when it is asked for (shape, then the
+// NRR_ARITH override, then the tuned table) or, by default, whenever it can:
+// 12-bit data, block edges 3-9, the whole window in LDS.
+static bool wants_mfma(nrr_dtype dtype, int32_t block, int32_t window, const TileShape *shape) {
+    if (!mfma_supported(dtype, block, window)) return false;
+    if (shape) return shape->arith == kArithMfma;
+    TileShape sh;
+    if (shape_from_env(&sh)) return false;
+    const int pref = arith_preference();
+    if (pref >= 0) return pref == kArithMfma;
+    if (tuned_shape(dtype, block, window, &sh)) return sh.arith == kArithMfma;
+    return true;
+}
+
 int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out, int cap) {
     const size_t limit = device_lds_limit();
     const int d = 2 * window + 1;
     int n = 0;
+    if (mfma_supported(dtype, block, window)) {
+        if (n < cap) out[n] = TileShape{kArithMfma, 0, 0, 256, -1, 0};
+        ++n;
+    }
     for (const Variant &v : kVariants) {
         if (v.dtype != dtype || v.b != block) continue;
         Plan pl;
@@ -1201,6 +1221,8 @@ int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out,
 
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
                         const TileShape *shape) {
+    if (mfma_fits(a) && wants_mfma(dtype, a.block, a.window, shape))
+        return launch_match_mfma(a, stream);
     Plan pl;
     if (!choose(dtype, a.block, a.window, device_lds_limit(), shape, &pl))
         return hipErrorInvalidValue;

@@ -159,7 +159,7 @@ bool plan_batch_set(nrr_dtype dtype, int32_t block, int32_t window, int32_t *var
 hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nsets,
                               int64_t nitems, size_t lds, hipStream_t stream);
 
-// A compiled search shape: arithmetic (0 dot2, 1 FMA, -1 any), tile rx x ry
+// A compiled search shape: arithmetic (0 dot2, 1 FMA, 2 MFMA, -1 any), tile rx x ry
 // (0: any), threads, record prefetch (-1 any) and z-chunk cap (0: planned).
 struct TileShape {
     int32_t arith, rx, ry, nt, pf, cz;
@@ -173,6 +173,13 @@ int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out,
 bool tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, TileShape *sh);
 void set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, const TileShape &sh);
 void clear_tuned_shapes();
+
+// The matrix-core form of the search (12-bit data, block edges 3-9, whole
+// window in LDS): whether it serves (dtype, block, window), and its launch.
+bool mfma_supported(nrr_dtype dtype, int32_t block, int32_t window);
+bool mfma_fits(const MatchArgs &a);  // volume small enough for its 32-bit indices
+hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream);
+constexpr int32_t kArithMfma = 2;  // TileShape::arith of the matrix-core form
 
 // LDS bytes per workgroup available on the current device (cached).
 size_t device_lds_limit();

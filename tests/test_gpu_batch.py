@@ -165,12 +165,10 @@ def test_tuner_keeps_results_and_records_shape(torch_dev, u16_pair):
     torch.cuda.synchronize()
     say("tuner u16 b7 w6")
     shape, us = nrr.tune_match(ref_d, flt_d, c, 7, 6, reps=2)
-    assert us > 0 and shape["rx"] > 0
+    assert us > 0 and (shape["rx"] > 0 or shape["arith"] == 2)  # 2: matrix-core form
     assert nrr.tuned_shape(nrr.U16, 7, 6) == shape
     d1, n1, f1 = nrr.block_match(ref_d, flt_d, c, 7, 6)
     torch.cuda.synchronize()
-    if shape["arith"] == 0:  # dot2 tuned: exact, identical to any dot2 shape
-        pass
     same_or_tied(to_host(d0), to_host(n0), to_host(d1), to_host(n1))
     check_match(p.ref, p.flt, to_host(c), 7, 6, to_host(d1), to_host(n1), to_host(f1), "tuned")
     nrr.clear_tuning()

@@ -3,7 +3,7 @@ blocks 9^3 on an overlapping stride-5 grid, F = 0.70 -> K = 357,035, window
 +-12), in the launch the benchmark times: the selection compared whole
 against the oracle, the search on a seeded sample of 2048 selected blocks
 (about a quarter of them near a face, with clipped windows) under the parity
-rule of the other GPU tests, with both forms of the cross-term arithmetic."""
+rule of the other GPU tests, with each form of the cross-term arithmetic."""
 
 import sys
 
@@ -48,7 +48,7 @@ def test_select_whole(dense):
     assert np.array_equal(got, want)
 
 
-@pytest.mark.parametrize("arith", ["dot2", "fma"])
+@pytest.mark.parametrize("arith", ["dot2", "fma", "mfma"])
 def test_match_sampled(dense, monkeypatch, arith):
     import torch
 
