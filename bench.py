@@ -48,6 +48,8 @@ ANISO_CFG = {"block": (7, 7, 3), "stride": (7, 7, 3), "fraction": 0.25, "window"
 # MI355X: 256 CUs x 2.4 GHz x 256 ops/clk/CU (2 multiply-adds per lane per
 # clock: packed FP32 FMA, or v_dot2_i32_i16) = the FP32 vector peak.
 PEAK_TOPS = 157.3
+# MI355X dense fp16 matrix-core peak (the matrix-core search's own dtype)
+PEAK_MFMA_F16_TFLOPS = 2500.0
 OPS_PER_PAIR = 2  # one multiply-add per (block voxel, displacement) pair
 
 
@@ -55,15 +57,18 @@ OPS_PER_PAIR = 2  # one multiply-add per (block voxel, displacement) pair
 # in profiles/ (one summary per workload); reported only while the kernel's
 # sources are unchanged.
 TRAFFIC_FILES = {
-    "mri_256x256x124_u16": ("k_match_u16_mri_256x256x124_traffic.json",
-                            ["paper_2308_10868_amd/csrc/match.hip",
-                             "paper_2308_10868_amd/csrc/nrr_internal.h"]),
-    "blobs_512x512x256_u16": ("k_match_u16_blobs_512x512x256_traffic.json",
-                              ["paper_2308_10868_amd/csrc/match.hip",
-                               "paper_2308_10868_amd/csrc/nrr_internal.h"]),
-    "mri_aniso_256x256x124_u16": ("k_match_aniso_u16_mri_256x256x124_traffic.json",
-                                  ["paper_2308_10868_amd/csrc/match_aniso.hip",
-                                   "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    ("mri_256x256x124_u16", "dot2"): ("k_match_u16_mri_256x256x124_traffic.json",
+                                      ["paper_2308_10868_amd/csrc/match.hip",
+                                       "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    ("blobs_512x512x256_u16", "dot2"): ("k_match_u16_blobs_512x512x256_traffic.json",
+                                        ["paper_2308_10868_amd/csrc/match.hip",
+                                         "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    ("mri_256x256x124_u16", "mfma"): ("k_match_mfma_mri_256x256x124_traffic.json",
+                                      ["paper_2308_10868_amd/csrc/match_mfma.hip",
+                                       "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    ("mri_aniso_256x256x124_u16", "fma"): ("k_match_aniso_u16_mri_256x256x124_traffic.json",
+                                           ["paper_2308_10868_amd/csrc/match_aniso.hip",
+                                            "paper_2308_10868_amd/csrc/nrr_internal.h"]),
 }
 
 
@@ -77,12 +82,13 @@ def kernel_source_hash(sources) -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, arith: str):
     """Bytes per search launch from the committed counter summary, or None
-    when it was taken on other sources or there is none for the workload."""
-    if workload not in TRAFFIC_FILES:
+    when it was taken on other sources or there is none for the workload and
+    arithmetic form."""
+    if (workload, arith) not in TRAFFIC_FILES:
         return None
-    name, sources = TRAFFIC_FILES[workload]
+    name, sources = TRAFFIC_FILES[(workload, arith)]
     try:
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
@@ -332,6 +338,23 @@ def main() -> int:
     lat = np.array(lat)
 
     achieved = OPS_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
+    arith = nrr.match_arith(dt_code, dims, b, w)
+    if arith == "mfma":
+        # fp16 matrix-core products of exact 12-bit offsets: judged against
+        # the fp16 MFMA peak, with the FP32-vector fraction beside it
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_F16_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / PEAK_MFMA_F16_TFLOPS,
+                    "traffic": measured_traffic(args.workload, arith),
+                    "kernel": "k_match_mfma<%d>" % b,
+                    "fp32_vector_equivalent": {"peak": PEAK_TOPS, "unit": "TOP/s",
+                                               "frac": achieved / PEAK_TOPS}}
+        dtype = "f16"
+    else:
+        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
+                    "frac": achieved / PEAK_TOPS,
+                    "traffic": measured_traffic(args.workload, arith),
+                    "kernel": "k_match_u16" if dt_code == nrr.U16 else "k_match_f32"}
+        dtype = ("int32" if arith == "dot2" else "f32")
     result = {
         "metric": "NCC voxel-pairs/s (block matching) at 1 GPU; p50/p99 registration latency",
         "value": pairs / (ms_step * 1e-3),
@@ -343,7 +366,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32" if dt_code == nrr.U16 else "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "dims_xyz": list(dims), "block": b,
                    "stride": stride, "fraction": frac, "window": w, "blocks": k,
@@ -361,9 +384,8 @@ def main() -> int:
         "selection_ms": {"mean": float(np.mean(select_ms)), "median": float(np.median(select_ms)),
                          "what": "select_blocks on the main stream, beside the window "
                                  "statistics on the second (eager steps)"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(args.workload),
-                     "kernel": "k_match_u16" if dt_code == nrr.U16 else "k_match_f32"},
+        "search_arith": arith,
+        "roofline": roofline,
     }
     if args.cpu_budget > 0:
         print("# timing the oracle (%.0f s budget)" % args.cpu_budget, file=sys.stderr, flush=True)
@@ -535,7 +557,7 @@ def bench_aniso(args) -> int:
                    "blocks": int(len(centers_h)), "evaluated_pairs": pairs, "seed": args.seed},
         "search_kernel_ms": kern_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(ANISO),
+                     "frac": achieved / PEAK_TOPS, "traffic": measured_traffic(ANISO, "fma"),
                      "kernel": "k_match_aniso"},
     }
     if args.cpu_budget > 0:

@@ -94,6 +94,17 @@ nrr_status nrr_match_workspace_bytes(nrr_dtype dtype, const int32_t dims[3], int
  * not fit in LDS), INVALID_ARG for malformed values. */
 nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window);
 
+/* Arithmetic form of the cross term that nrr_block_match would launch now
+ * for these arguments on the current device (host-only, no device work):
+ * *arith = 0 exact int16 dot2 (12-bit data), 1 FP32 FMA, 2 fp16 matrix-core
+ * products of exact 12-bit offsets with FP32 sums (12-bit data, block edges
+ * 3-9, the window in LDS; the default where it serves).  The NRR_ARITH
+ * environment override (dot2 | fma | mfma) and shapes chosen by
+ * nrr_tune_match are taken into account.  Errors as nrr_match_supported;
+ * INVALID_ARG for NULL pointers. */
+nrr_status nrr_match_arith(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
+                           int32_t *arith);
+
 /* ---------------------------------------------------------------- selection
  * Variance-ranked block selection ("Parallel feature selection" paragraph:
  * each candidate block's intensity variance is computed, the candidates are

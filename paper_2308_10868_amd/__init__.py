@@ -127,6 +127,7 @@ def load():
         "nrr_select_workspace_bytes": (st, [P, I32, I32, P]),
         "nrr_match_workspace_bytes": (st, [ctypes.c_int, P, I32, P]),
         "nrr_match_supported": (st, [ctypes.c_int, I32, I32]),
+        "nrr_match_arith": (st, [ctypes.c_int, P, I32, I32, P]),
         "nrr_select_blocks": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P, SZ, P]),
         "nrr_block_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, P]),
         "nrr_select_blocks_ex": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I32, P, I64, P, P, SZ,
@@ -209,6 +210,18 @@ def match_supported(dtype: int, block: int, window: int) -> bool:
 
 
 # --------------------------------------------------------------- tensors
+
+ARITH_NAMES = {0: "dot2", 1: "fma", 2: "mfma"}
+
+
+def match_arith(dtype: int, dims, block: int, window: int) -> str:
+    """Arithmetic form of the cross term nrr_block_match would launch now:
+    'dot2', 'fma' or 'mfma' (environment override and tuned shapes included)."""
+    lib = load()
+    a = ctypes.c_int32(-1)
+    _check(lib.nrr_match_arith(dtype, _dims3(dims), block, window, ctypes.byref(a)))
+    return ARITH_NAMES.get(a.value, str(a.value))
+
 
 def _torch():
     import torch

@@ -136,6 +136,25 @@ nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window) {
     return ok();
 }
 
+nrr_status nrr_match_arith(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
+                           int32_t *arith) {
+    if (!dims || !arith) return fail(NRR_ERR_INVALID_ARG, "dims and arith must be non-NULL");
+    nrr_status s = nrr_match_supported(dtype, block, window);
+    if (s != NRR_OK) return s;
+    int32_t g[3];
+    if ((s = check_grid(dims, block, 1, g)) != NRR_OK) return s;
+    nrr::MatchArgs a{};
+    a.nx = dims[0];
+    a.ny = dims[1];
+    a.nz = dims[2];
+    a.block = block;
+    a.window = window;
+    a.ox = dims[0] - block + 1;
+    a.oy = dims[1] - block + 1;
+    *arith = nrr::match_arith(dtype, a);
+    return ok();
+}
+
 nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                              int32_t block, int32_t stride, double fraction, int32_t *centers,
                              int64_t capacity, int64_t *k_out, void *workspace,

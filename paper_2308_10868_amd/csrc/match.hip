@@ -1219,6 +1219,13 @@ int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out,
     return n < cap ? n : cap;
 }
 
+int match_arith(nrr_dtype dtype, const MatchArgs &a) {
+    if (mfma_fits(a) && wants_mfma(dtype, a.block, a.window, nullptr)) return kArithMfma;
+    Plan pl;
+    if (!choose(dtype, a.block, a.window, device_lds_limit(), nullptr, &pl)) return -1;
+    return pl.v->arith;
+}
+
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
                         const TileShape *shape) {
     if (mfma_fits(a) && wants_mfma(dtype, a.block, a.window, shape))

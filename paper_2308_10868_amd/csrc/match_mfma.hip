@@ -40,6 +40,10 @@
 //    balance over the workgroup's wavefronts;
 //  * argmax: largest key, smallest shift index among equal keys, reduced over
 //    lanes, wavefronts and the workgroup.
+//
+// One 256-thread workgroup per selected block, two co-resident per CU: the
+// staging and ranking latencies of one are hidden behind the matrix work of
+// the other.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -62,9 +66,7 @@ typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef short i16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 half4u __attribute__((ext_vector_type(4), aligned(2)));
 
-constexpr int MF_NT = 256;  // threads per workgroup (4 wavefronts)
-constexpr int MF_NW = MF_NT / 64;
-constexpr int OFF = 3;      // zero border of the T table (offsets 0..3)
+constexpr int OFF = 3;  // zero border of the T table (offsets 0..3)
 
 // Compile-time sizes of the K layout for block edge B.
 template <int B>
@@ -75,6 +77,8 @@ struct KGeo {
     static constexpr int NQ = (NG + 3) / 4;      // 32-wide K chunks per block plane
     static constexpr int TXW = 4 * GX + 4;       // T table row width (halves)
     static constexpr int TYW = 2 * GYP + OFF;    // T table rows per plane
+    static constexpr int TT_HALVES = B * TYW * TXW;
+    static constexpr int TT_BYTES = (TT_HALVES * 2 + 15) & ~15;
 };
 
 struct MfParams {
@@ -82,11 +86,11 @@ struct MfParams {
     const uint16_t *flt;
     int nx, ny, nz;
     const int32_t *centers;
-    int64_t first;
+    int64_t first;  // first block of this launch
     int w;
     const StatU16 *stats;
     int ox, oy;
-    int rp, pl;  // LDS window row pitch and plane pitch (halves)
+    int rp, pl;  // LDS window row and plane pitch (halves)
     int32_t *disp;
     float *ncc;
     float *conf;
@@ -98,7 +102,7 @@ __device__ inline int64_t xcd_order(int64_t wg, int64_t n) {
 }
 
 __device__ inline void keep_best(float &bk, int &bi, float k, int i) {
-    const bool take = k > bk || (k == bk && i < bi);
+    const bool take = (k > bk) | ((k == bk) & (i < bi));  // no short-circuit branches
     bk = take ? k : bk;
     bi = take ? i : bi;
 }
@@ -111,11 +115,12 @@ __device__ inline void put(const MfParams &p, int64_t blk, int dx, int dy, int d
     p.conf[blk] = v > 0.0f ? v : 0.0f;
 }
 
+constexpr int MAX_NW = 4;  // wavefronts per workgroup
 struct MfSmall {
-    long long red[MF_NW * 4];
-    int mm[MF_NW * 2];
-    float key[MF_NW];
-    int idx[MF_NW];
+    long long red[MAX_NW * 4];
+    int mm[MAX_NW * 2];
+    float key[MAX_NW];
+    int idx[MAX_NW];
 };
 
 // Tile decomposition of one block's displacements: bases every 4 voxels in x
@@ -126,7 +131,7 @@ struct Tiling {
     int nbx, nby, nxy, nph, tz, nrows, ntiles;
 };
 
-__device__ inline Tiling make_tiling(int dxn, int dyn, int dzn, int b, int nq) {
+__device__ inline Tiling make_tiling(int dxn, int dyn, int dzn, int b, int nq, int nw) {
     Tiling t;
     t.nbx = (dxn + 3) / 4;
     t.nby = (dyn + 3) / 4;
@@ -137,7 +142,7 @@ __device__ inline Tiling make_tiling(int dxn, int dyn, int dzn, int b, int nq) {
     for (int tz = b; tz < dzn + b; tz += b) {
         const int ph = (dzn + tz - 1) / tz;
         const int tiles = (t.nxy * ph + 15) / 16;
-        const int rounds = (tiles + MF_NW - 1) / MF_NW;
+        const int rounds = (tiles + nw - 1) / nw;
         const float c = rounds * ((float)tz * b * nq + 3.0f * (tz + b - 1));
         if (c < bc) {
             bc = c;
@@ -149,6 +154,84 @@ __device__ inline Tiling make_tiling(int dxn, int dyn, int dzn, int b, int nq) {
     t.nrows = t.nxy * t.nph;
     t.ntiles = (t.nrows + 15) / 16;
     return t;
+}
+
+// Search geometry of one block: valid displacement range per axis (the
+// displaced block inside the volume), the window origin, and the staged
+// region.  Rows are staged from the even element at or before the window's
+// first column (4-byte aligned copies; volumes with an even row length), so
+// window column x sits at LDS column x + px; the tiles' x bases are LDS
+// columns 4i (8-byte aligned operand reads).
+struct BGeo {
+    int cx, cy, cz;
+    bool inside;
+    int lox, loy, loz, dxn, dyn, dzn;
+    int wx0, wy0, wz0, ex, ey, ez, px;
+    int rpb, pyb, cpr;  // LDS columns read, staged rows per plane, 8-column chunks per row
+    Tiling tl;
+};
+
+template <int B>
+__device__ inline BGeo block_geo(const MfParams &p, int64_t blk, int nw) {
+    using G = KGeo<B>;
+    constexpr int H = (B - 1) / 2;
+    BGeo g;
+    g.cx = p.centers[3 * blk];
+    g.cy = p.centers[3 * blk + 1];
+    g.cz = p.centers[3 * blk + 2];
+    g.inside = g.cx - H >= 0 && g.cy - H >= 0 && g.cz - H >= 0 && g.cx + H <= p.nx - 1 &&
+               g.cy + H <= p.ny - 1 && g.cz + H <= p.nz - 1;
+    g.lox = max(-p.w, H - g.cx);
+    g.loy = max(-p.w, H - g.cy);
+    g.loz = max(-p.w, H - g.cz);
+    g.dxn = min(p.w, p.nx - 1 - H - g.cx) - g.lox + 1;
+    g.dyn = min(p.w, p.ny - 1 - H - g.cy) - g.loy + 1;
+    g.dzn = min(p.w, p.nz - 1 - H - g.cz) - g.loz + 1;
+    g.wx0 = g.cx - H + g.lox;
+    g.wy0 = g.cy - H + g.loy;
+    g.wz0 = g.cz - H + g.loz;
+    g.ex = g.dxn + B - 1;
+    g.ey = g.dyn + B - 1;
+    g.ez = g.dzn + B - 1;
+    g.px = (p.nx & 1) == 0 ? (g.wx0 & 1) : 0;
+    g.tl = make_tiling(g.dxn + g.px, g.dyn, g.dzn, B, G::NQ, nw);
+    g.rpb = 4 * (g.tl.nbx - 1) + 4 * G::GX;
+    g.pyb = 4 * (g.tl.nby - 1) + 2 * G::GYP;
+    g.cpr = (g.rpb + 7) / 8;
+    return g;
+}
+
+// Global element of LDS column 8 xc, row y, plane z of the staged region
+// (rows past the window repeat its last row).
+__device__ inline int64_t stage_elem(const MfParams &p, const BGeo &g, int z, int y, int xc) {
+    return ((int64_t)(g.wz0 + z) * p.ny + (g.wy0 + min(y, g.ey - 1))) * p.nx + g.wx0 - g.px +
+           8 * xc;
+}
+
+// The 16 bytes (8 voxels) of one staged chunk through registers: a 16-byte
+// load where it lies inside the volume, else clamped words (the volume's
+// last voxels) or, for odd row lengths, voxel by voxel clamped into the
+// window's row.
+__device__ inline u32x4 load_chunk(const MfParams &p, const BGeo &g, int64_t e, int xc) {
+    const int64_t vol_end = (int64_t)p.nx * p.ny * p.nz - 1;
+    if ((p.nx & 1) == 0 && e + 7 <= vol_end) return *reinterpret_cast<const u32x4 *>(p.flt + e);
+    uint32_t t[4];
+    if ((p.nx & 1) == 0) {
+        const int64_t last_pair = (vol_end - 1) & ~(int64_t)1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            t[j] = *reinterpret_cast<const uint32_t *>(p.flt + min(e + 2 * j, last_pair));
+    } else {
+        const uint16_t *r = p.flt + (e - 8 * xc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x0 = min(8 * xc + 2 * j, g.ex - 1), x1 = min(8 * xc + 2 * j + 1, g.ex - 1);
+            t[j] = (uint32_t)r[x0] | ((uint32_t)r[x1] << 16);
+        }
+    }
+    u32x4 v;
+    __builtin_memcpy(&v, t, 16);
+    return v;
 }
 
 // One unrolled block of B sweep steps t0 .. t0 + B - 1 (t0 a multiple of B):
@@ -164,10 +247,14 @@ __device__ __attribute__((always_inline)) inline void sweep_block(
 #pragma unroll
     for (int u = 0; u < STEPS; ++u) {
         const int t = t0 + u;
+        // consecutive products feed different accumulators, and the plane
+        // completed by this step (block plane B - 1) is fed first in each
+        // chunk, so its sums are ready when the ranking reads them
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)  // consecutive products feed different accumulators
+        for (int q = 0; q < NQ; ++q)
 #pragma unroll
-            for (int s = 0; s < B; ++s) {
+            for (int k = 0; k < B; ++k) {
+                const int s = B - 1 - k;
                 if (MODE == 0 && s > u) continue;
                 if (MODE == 2 && s <= u) continue;
                 const int slot = (u - s + B) % B;
@@ -183,115 +270,316 @@ __device__ __attribute__((always_inline)) inline void sweep_block(
     }
 }
 
-// Two wavefronts per SIMD up to 7^3 blocks; the 9^3 block's B operands
-// (180 registers) take the whole register file of one.
+// Toeplitz B operands of this lane for every block plane and K chunk, from
+// the zero-bordered table of T - c.
 template <int B>
-__global__ __launch_bounds__(MF_NT, B <= 7 ? 2 : 1) void k_match_mfma(MfParams p) {
+__device__ __attribute__((always_inline)) inline void build_bop(
+    const _Float16 *tt, int lane, half8 (&bop)[B][KGeo<B>::NQ]) {
     using G = KGeo<B>;
-    constexpr int H = (B - 1) / 2, N = B * B * B, NQ = G::NQ;
+    const int grp = lane >> 4, oa = lane & 3, ob = (lane >> 2) & 3;  // column: offset (oa, ob)
+#pragma unroll
+    for (int q = 0; q < G::NQ; ++q) {
+        const int g = 4 * q + grp;
+        const bool real = g < G::NG;
+        const int gx = real ? g % G::GX : 0, gy = real ? g / G::GX : 0;
+#pragma unroll
+        for (int s = 0; s < B; ++s) {
+            const _Float16 *tr = tt + (s * G::TYW + 2 * gy - ob + OFF) * G::TXW + 4 * gx - oa + OFF;
+            const half4u lo = *reinterpret_cast<const half4u *>(tr);
+            const half4u hi = *reinterpret_cast<const half4u *>(tr + G::TXW);
+            const half8 v = half8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            bop[s][q] = real ? v : half8{};
+        }
+    }
+}
+
+// This wavefront's tiles of the block's search over the centred window
+// `win` (row pitch rp, plane pitch pl halves): keeps the lane's best (key,
+// shift index).  key = (N C - S_T S_F) * rsqrt(N varF), with S_T = sum (T -
+// c) and S_F = sum (F - c) = s + N (2048 - c) (the table's s sums F - 2048):
+// S_T S_F = S_T s + S_T N (2048 - c), both terms in FP32 from exact integers
+// (relative error 2^-24 of terms that are at most N^2 2048^2).
+template <int B, int NW>
+__device__ __attribute__((always_inline)) inline void sweep_tiles(
+    const MfParams &p, const BGeo &g, const _Float16 *win, int rp, int pl,
+    const half8 (&bop)[B][KGeo<B>::NQ], long long sTc, int c, int wave, int lane, float &bk,
+    int &bi) {
+    using G = KGeo<B>;
+    constexpr int N = B * B * B, NQ = G::NQ;
+    const Tiling &tl = g.tl;
+    const int n16 = lane & 15, grp = lane >> 4;
+    const int oa = n16 & 3, ob = n16 >> 2;
+    const float fN = (float)N, fST = (float)sTc;
+    const float fshift = (float)(sTc * (long long)N * (2048 - c));
+    const int side = 2 * p.w + 1, side2 = side * side;
+    const int plane_rec = p.oy * p.ox;
+    for (int tile = wave; tile < tl.ntiles; tile += NW) {
+        // the lane's A row (base of row n16)
+        int aoff[NQ], aph;
+        {
+            const int r = 16 * tile + n16, rr = r < tl.nrows ? r : 0;
+            const int xy = rr % tl.nxy, ph = rr / tl.nxy;
+            const int bx = 4 * (xy % tl.nbx), by = 4 * (xy / tl.nbx);
+            aph = ph * tl.tz;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int gg = 4 * q + grp < G::NG ? 4 * q + grp : 0;
+                aoff[q] = (by + 2 * (gg / G::GX)) * rp + bx + 4 * (gg % G::GX);
+            }
+        }
+        // the lane's four output rows: displacement (odx, ody) relative to the
+        // valid range's corner, plane offset oph; records at orec + dz planes
+        int odx[4], ody[4], oph[4], orec[4], oxy[4];
+        bool orow[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = 16 * tile + 4 * grp + i;
+            orow[i] = r < tl.nrows;
+            const int rr = orow[i] ? r : 0;
+            const int xy = rr % tl.nxy, ph = rr / tl.nxy;
+            odx[i] = 4 * (xy % tl.nbx) + oa - g.px;
+            ody[i] = 4 * (xy / tl.nbx) + ob;
+            oph[i] = ph * tl.tz;
+            orow[i] = orow[i] && odx[i] >= 0 && odx[i] < g.dxn && ody[i] < g.dyn;
+            orec[i] = (g.wz0 * p.oy + (g.wy0 + min(ody[i], g.dyn - 1))) * p.ox +
+                      (g.wx0 + min(max(odx[i], 0), g.dxn - 1));
+            oxy[i] = (g.loy + ody[i] + p.w) * side + (g.lox + odx[i] + p.w);
+        }
+        float4v acc[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) acc[k] = float4v{0.0f, 0.0f, 0.0f, 0.0f};
+        // A operand of plane t + phase (clamped: planes past the window feed
+        // only displacements that are masked out)
+        auto load_a = [&](int t, half8 (&aop)[NQ]) {
+            const int pz = min(t + aph, g.ez - 1);
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const _Float16 *ap = win + pz * pl + aoff[q];
+                const half4 lo = *reinterpret_cast<const half4 *>(ap);
+                const half4 hi = *reinterpret_cast<const half4 *>(ap + rp);
+                aop[q] = half8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            }
+        };
+        // statistics records of the four output rows, loaded one displacement
+        // plane ahead of their ranking (clamped into the valid range, so every
+        // load is in bounds; invalid ones are masked)
+        StatU16 rec0[4];
+        auto fetch = [&](int tau, StatU16 (&rec)[4]) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                rec[i] = p.stats[orec[i] + min(tau + oph[i], g.dzn - 1) * plane_rec];
+        };
+        // ranking of displacement plane tau, then the records of tau + 1
+        auto rank = [&](const float4v &c4, int tau) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int dz = tau + oph[i];
+                const float sts = __builtin_fmaf(fST, (float)rec0[i].s, fshift);
+                const float cov = __builtin_fmaf(fN, c4[i], -sts);
+                const bool valid = orow[i] && dz < g.dzn;
+                const float key = valid ? cov * rec0[i].r : -INFINITY;
+                const int idx = valid ? (g.loz + dz + p.w) * side2 + oxy[i] : INT_MAX;
+                keep_best(bk, bi, key, idx);
+            }
+            fetch(tau + 1, rec0);
+        };
+        fetch(0, rec0);
+        half8 aop[NQ];
+        load_a(0, aop);
+        sweep_block<B, NQ, 0>(0, acc, bop, aop, load_a, rank);
+        for (int t0 = B; t0 < tl.tz; t0 += B) sweep_block<B, NQ, 1>(t0, acc, bop, aop, load_a, rank);
+        sweep_block<B, NQ, 2>(tl.tz, acc, bop, aop, load_a, rank);
+    }
+}
+
+// Workgroup argmax of the lanes' (key, index), then the exact NCC at the
+// winner from the staged integers (v - c), written by thread 0.  Every
+// thread of the workgroup calls it; it ends with a barrier.
+template <int B, int NW>
+__device__ __attribute__((always_inline)) inline void finish_block(
+    const MfParams &p, const BGeo &g, int64_t blk, const _Float16 *win, int rp, int pl,
+    const _Float16 *tt, long long st, long long stt, int c, float bk, int bi, MfSmall &sm,
+    int tid) {
+    using G = KGeo<B>;
+    constexpr int N = B * B * B, NT = 64 * NW;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int off = 32; off > 0; off >>= 1) {
+        const float ok = __shfl_xor(bk, off);
+        const int oi = __shfl_xor(bi, off);
+        keep_best(bk, bi, ok, oi);
+    }
+    if (lane == 0) {
+        sm.key[wave] = bk;
+        sm.idx[wave] = bi;
+    }
+    __syncthreads();
+    bk = sm.key[0];
+    bi = sm.idx[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) keep_best(bk, bi, sm.key[i], sm.idx[i]);
+    if (bi == INT_MAX) {  // no finite key (cannot happen for 12-bit data)
+        if (tid == 0) put(p, blk, 0, 0, 0, NAN);
+        __syncthreads();
+        return;
+    }
+    const int side = 2 * p.w + 1;
+    const int ddx = bi % side - p.w, ddy = (bi / side) % side - p.w, ddz = bi / (side * side) - p.w;
+    const int rx = ddx - g.lox + g.px, ry = ddy - g.loy, rz = ddz - g.loz;
+    long long sf = 0, sff = 0, stf = 0;
+    for (int o = tid; o < N; o += NT) {
+        const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
+        const long long f = (long long)(float)win[(rz + oz) * pl + (ry + oy) * rp + rx + ox];
+        const long long tv = (long long)(float)tt[(oz * G::TYW + oy + OFF) * G::TXW + ox + OFF];
+        sf += f;
+        sff += f * f;
+        stf += tv * f;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sf += __shfl_xor(sf, off);
+        sff += __shfl_xor(sff, off);
+        stf += __shfl_xor(stf, off);
+    }
+    __syncthreads();  // sm reused
+    if (lane == 0) {
+        sm.red[wave * 4] = sf;
+        sm.red[wave * 4 + 1] = sff;
+        sm.red[wave * 4 + 2] = stf;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        sf = sff = stf = 0;
+        for (int i = 0; i < NW; ++i) {
+            sf += sm.red[i * 4];
+            sff += sm.red[i * 4 + 1];
+            stf += sm.red[i * 4 + 2];
+        }
+        const long long sTc = st - (long long)N * c;                       // sum (T - c)
+        const long long tc2 = stt - 2ll * c * st + (long long)N * c * c;  // sum (T - c)^2
+        const long long vt = (long long)N * tc2 - sTc * sTc;
+        const long long vf = (long long)N * sff - sf * sf;
+        const long long cv = (long long)N * stf - sTc * sf;
+        const double v = (vt > 0 && vf > 0) ? (double)cv / sqrt((double)vt * (double)vf) : 0.0;
+        put(p, blk, ddx, ddy, ddz, (float)v);
+    }
+    __syncthreads();
+}
+
+// Workgroup reduction of the block sums and the value range; every thread
+// returns the totals.
+template <int NW>
+__device__ inline void reduce_block(long long &st, long long &stt, int &vmin, int &vmax,
+                                    MfSmall &sm, int tid) {
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (int off = 32; off > 0; off >>= 1) {
+        st += __shfl_xor(st, off);
+        stt += __shfl_xor(stt, off);
+        vmin = min(vmin, __shfl_xor(vmin, off));
+        vmax = max(vmax, __shfl_xor(vmax, off));
+    }
+    if (lane == 0) {
+        sm.red[wave * 4] = st;
+        sm.red[wave * 4 + 1] = stt;
+        sm.mm[wave * 2] = vmin;
+        sm.mm[wave * 2 + 1] = vmax;
+    }
+    __syncthreads();
+    st = 0;
+    stt = 0;
+    vmin = 4095;
+    vmax = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        st += sm.red[i * 4];
+        stt += sm.red[i * 4 + 1];
+        vmin = min(vmin, sm.mm[i * 2]);
+        vmax = max(vmax, sm.mm[i * 2 + 1]);
+    }
+}
+
+// The centre: the block's rounded mean, clamped so every |v - c| <= 2048
+// over the staged voxels (12-bit values, so the interval is never empty).
+__device__ inline int centre(long long st, int n, int vmin, int vmax) {
+    return min(max((int)llrint((double)st / (double)n), vmax - 2048), vmin + 2048);
+}
+
+// 16 bytes of raw 12-bit voxels -> fp16 (v - c), exact for |v - c| <= 2048.
+__device__ inline u32x4 centre_chunk(u32x4 v, i16x2 c2) {
+    i16x2 d[4];
+    half2v h[4];
+    __builtin_memcpy(d, &v, 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j] = __builtin_convertvector(d[j] - c2, half2v);
+    __builtin_memcpy(&v, h, 16);
+    return v;
+}
+
+// ------------------------------------------------------------------ kernel
+// One 256-thread workgroup per selected block.  Two wavefronts per SIMD up
+// to 7^3 blocks; the 9^3 block's B operands (180 registers) take the whole
+// register file of one.
+constexpr int PB_NW = 4;
+
+template <int B>
+__global__ __launch_bounds__(64 * PB_NW, B <= 7 ? 2 : 1) void k_match_mfma(MfParams p) {
+    using G = KGeo<B>;
+    constexpr int H = (B - 1) / 2, N = B * B * B, NQ = G::NQ, NT = 64 * PB_NW;
     extern __shared__ __align__(16) unsigned char lds[];
     __shared__ MfSmall sm;
     _Float16 *tt = reinterpret_cast<_Float16 *>(lds);  // [B][TYW][TXW]
-    constexpr int TT_HALVES = B * G::TYW * G::TXW;
-    _Float16 *win = reinterpret_cast<_Float16 *>(lds + ((TT_HALVES * 2 + 15) & ~15));
+    _Float16 *win = reinterpret_cast<_Float16 *>(lds + G::TT_BYTES);
 
     const int64_t blk = p.first + xcd_order(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cx = p.centers[3 * blk], cy = p.centers[3 * blk + 1], cz = p.centers[3 * blk + 2];
-    const bool inside = cx - H >= 0 && cy - H >= 0 && cz - H >= 0 && cx + H <= p.nx - 1 &&
-                        cy + H <= p.ny - 1 && cz + H <= p.nz - 1;
-    if (!inside) {
+    const BGeo g = block_geo<B>(p, blk, PB_NW);
+    if (!g.inside) {
         if (tid == 0) put(p, blk, 0, 0, 0, NAN);
         return;
     }
-    const int lox = max(-p.w, H - cx), loy = max(-p.w, H - cy), loz = max(-p.w, H - cz);
-    const int dxn = min(p.w, p.nx - 1 - H - cx) - lox + 1;
-    const int dyn = min(p.w, p.ny - 1 - H - cy) - loy + 1;
-    const int dzn = min(p.w, p.nz - 1 - H - cz) - loz + 1;
-    const int wx0 = cx - H + lox, wy0 = cy - H + loy, wz0 = cz - H + loz;
-    const int ex = dxn + B - 1, ey = dyn + B - 1, ez = dzn + B - 1;  // window extents
-    // Rows are staged from the even element at or before the window's first
-    // column (4-byte aligned loads; volumes with an even row length), so the
-    // window's column x sits at LDS column x + px; the x bases of the tiles
-    // are LDS columns 4i (8-byte aligned operand reads).
-    const bool even_rows = (p.nx & 1) == 0;
-    const int px = even_rows ? (wx0 & 1) : 0;
-    const Tiling tl = make_tiling(dxn + px, dyn, dzn, B, NQ);
-    const int rpb = 4 * (tl.nbx - 1) + 4 * G::GX;  // LDS columns read (halves)
-    const int pyb = 4 * (tl.nby - 1) + 2 * G::GYP;  // staged rows per plane
     const int rp = p.rp, pl = p.pl;
-    const int cpr = (rpb + 7) / 8;                  // 8-column chunks per staged row
-    const int nchunk = ez * pyb * cpr;
+    const int nchunk = g.ez * g.pyb * g.cpr;
 
     // ---- pass 1: window as raw 12-bit values, block sums, value range.  The
     // block's voxels (at most 3 per thread for edges up to 9) are loaded with
     // the first round of window rows and kept in registers for pass 2.
-    for (int i = tid; i < TT_HALVES; i += MF_NT) tt[i] = (_Float16)0.0f;
-    constexpr int TPT = (N + MF_NT - 1) / MF_NT;  // block voxels per thread
+    for (int i = tid; i < G::TT_HALVES; i += NT) tt[i] = (_Float16)0.0f;
+    constexpr int TPT = (N + NT - 1) / NT;  // block voxels per thread
     int tv[TPT];
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
-        const int o = min(tid + k * MF_NT, N - 1);
+        const int o = min(tid + k * NT, N - 1);
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        tv[k] = p.ref[((int64_t)(cz - H + oz) * p.ny + (cy - H + oy)) * p.nx + (cx - H + ox)];
+        tv[k] = p.ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx + (g.cx - H + ox)];
     }
     // The range that clamps the centre covers every staged voxel: the window
-    // and the few neighbouring voxels its padded rows pick up (12-bit values
-    // all, so the clamp interval stays non-empty).
+    // and the few neighbouring voxels its padded rows pick up.
     u16x2 mn2 = {4095, 4095}, mx2 = {0, 0};
     {
-        const int64_t vol_end = (int64_t)p.nx * p.ny * p.nz - 1;
-        const int64_t last_pair = (vol_end - 1) & ~(int64_t)1;  // last aligned 2-voxel word
-        // chunk coordinates advance by MF_NT chunks per step (no divisions)
-        const int sx = MF_NT % cpr, sr = MF_NT / cpr;
-        int xc = tid % cpr, y = tid / cpr, z = 0;
-        while (y >= pyb) {
-            y -= pyb;
+        // chunk coordinates advance by NT chunks per step (no divisions)
+        const int sx = NT % g.cpr, sr = NT / g.cpr;
+        int xc = tid % g.cpr, y = tid / g.cpr, z = 0;
+        while (y >= g.pyb) {
+            y -= g.pyb;
             ++z;
         }
         constexpr int UNR = 8;
-        for (int c0 = tid; c0 < nchunk; c0 += MF_NT * UNR) {
+        for (int c0 = tid; c0 < nchunk; c0 += NT * UNR) {
             u32x4 w[UNR];
             int off[UNR];
             bool live[UNR];
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
-                live[u] = c0 + u * MF_NT < nchunk;
+                live[u] = c0 + u * NT < nchunk;
                 const int zz = live[u] ? z : 0;
                 off[u] = zz * pl + y * rp + 8 * xc;
-                // element of LDS column 8 xc of this row (rows past the window
-                // repeat its last row)
-                const int64_t e = ((int64_t)(wz0 + zz) * p.ny + (wy0 + min(y, ey - 1))) * p.nx +
-                                  wx0 - px + 8 * xc;
-                if (even_rows && e + 7 <= vol_end) {  // one 16-byte load
-                    w[u] = *reinterpret_cast<const u32x4 *>(p.flt + e);
-                } else {
-                    uint32_t t[4];
-                    if (even_rows) {  // the volume's last voxels: clamped words
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int64_t a = min(e + 2 * j, last_pair);
-                            t[j] = *reinterpret_cast<const uint32_t *>(p.flt + a);
-                        }
-                    } else {  // odd row length: voxel by voxel, clamped into the window
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const int x0 = min(8 * xc + 2 * j, ex - 1);
-                            const int x1 = min(8 * xc + 2 * j + 1, ex - 1);
-                            const uint16_t *r = p.flt + (e - 8 * xc);
-                            t[j] = (uint32_t)r[x0] | ((uint32_t)r[x1] << 16);
-                        }
-                    }
-                    __builtin_memcpy(&w[u], t, 16);
-                }
+                w[u] = load_chunk(p, g, stage_elem(p, g, zz, y, xc), xc);
                 xc += sx;
                 y += sr;
-                if (xc >= cpr) {
-                    xc -= cpr;
+                if (xc >= g.cpr) {
+                    xc -= g.cpr;
                     ++y;
                 }
-                while (y >= pyb) {
-                    y -= pyb;
+                while (y >= g.pyb) {
+                    y -= g.pyb;
                     ++z;
                 }
             }
@@ -313,250 +601,56 @@ __global__ __launch_bounds__(MF_NT, B <= 7 ? 2 : 1) void k_match_mfma(MfParams p
     long long st = 0, stt = 0;
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
-        if (tid + k * MF_NT >= N) continue;
+        if (tid + k * NT >= N) continue;
         st += tv[k];
         stt += (long long)tv[k] * tv[k];
         vmin = min(vmin, tv[k]);
         vmax = max(vmax, tv[k]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        st += __shfl_xor(st, off);
-        stt += __shfl_xor(stt, off);
-        vmin = min(vmin, __shfl_xor(vmin, off));
-        vmax = max(vmax, __shfl_xor(vmax, off));
-    }
-    if (lane == 0) {
-        sm.red[wave * 4] = st;
-        sm.red[wave * 4 + 1] = stt;
-        sm.mm[wave * 2] = vmin;
-        sm.mm[wave * 2 + 1] = vmax;
-    }
-    __syncthreads();
-    st = 0;
-    stt = 0;
-    vmin = 4095;
-    vmax = 0;
-#pragma unroll
-    for (int i = 0; i < MF_NW; ++i) {
-        st += sm.red[i * 4];
-        stt += sm.red[i * 4 + 1];
-        vmin = min(vmin, sm.mm[i * 2]);
-        vmax = max(vmax, sm.mm[i * 2 + 1]);
-    }
+    reduce_block<PB_NW>(st, stt, vmin, vmax, sm, tid);
     if ((long long)N * stt - st * st == 0) {  // flat block: every NCC is 0
-        if (tid == 0) put(p, blk, lox, loy, loz, 0.0f);
+        if (tid == 0) put(p, blk, g.lox, g.loy, g.loz, 0.0f);
         return;
     }
-    // centre: the block's rounded mean, clamped so every |v - c| <= 2048
-    // over the block and its window
-    const int c = min(max((int)llrint((double)st / (double)N), vmax - 2048), vmin + 2048);
+    const int c = centre(st, N, vmin, vmax);
 
     // ---- pass 2: centre the staged planes in place (whole planes, padding
-    // included: those halves are never read) and write T - c into the
-    // bordered table
+    // included: those halves are never read) and the bordered table of T - c
     {
         const i16x2 c2 = {(short)c, (short)c};
-        const int nq = ez * pl / 8;  // pl is a multiple of 8 halves
-        for (int i = tid; i < nq; i += MF_NT) {
+        const int nq = g.ez * pl / 8;  // pl is a multiple of 8 halves
+        for (int i = tid; i < nq; i += NT) {
             u32x4 *a = reinterpret_cast<u32x4 *>(win + 8 * i);
-            u32x4 v = *a;
-            i16x2 d[4];
-            half2v h[4];
-            __builtin_memcpy(d, &v, 16);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)  // |d - c| <= 2048 in the window: exact
-                h[j] = __builtin_convertvector(d[j] - c2, half2v);
-            __builtin_memcpy(&v, h, 16);
-            *a = v;
+            *a = centre_chunk(*a, c2);
         }
     }
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
-        const int o = tid + k * MF_NT;
+        const int o = tid + k * NT;
         if (o >= N) continue;
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
         tt[(oz * G::TYW + oy + OFF) * G::TXW + ox + OFF] = (_Float16)(float)(tv[k] - c);
     }
     __syncthreads();
 
-    // ---- Toeplitz B operands of this lane, for every block plane and chunk
-    const int n16 = lane & 15, grp = lane >> 4;
-    const int oa = n16 & 3, ob = n16 >> 2;  // the lane's column: offset (oa, ob)
     half8 bop[B][NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int g = 4 * q + grp;
-        const bool real = g < G::NG;
-        const int gx = real ? g % G::GX : 0, gy = real ? g / G::GX : 0;
-#pragma unroll
-        for (int s = 0; s < B; ++s) {
-            const _Float16 *tr = tt + (s * G::TYW + 2 * gy - ob + OFF) * G::TXW + 4 * gx - oa + OFF;
-            const half4u lo = *reinterpret_cast<const half4u *>(tr);
-            const half4u hi = *reinterpret_cast<const half4u *>(tr + G::TXW);
-            const half8 v = half8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-            bop[s][q] = real ? v : half8{};
-        }
-    }
-
-    // ---- sweep
-    // key = (N C - S_T S_F) * rsqrt(N varF), with S_T = sum (T - c) and
-    // S_F = sum (F - c) = s + N (2048 - c) (the table's s sums F - 2048):
-    // S_T S_F = S_T s + S_T N (2048 - c), both terms in FP32 from exact
-    // integers (relative error 2^-24 of terms that are at most N^2 2048^2)
-    const long long sTc = st - (long long)N * c;          // sum (T - c)
-    const float fN = (float)N, fST = (float)sTc;
-    const float fshift = (float)(sTc * (long long)N * (2048 - c));
-    const int side = 2 * p.w + 1, side2 = side * side;
-    const int plane_rec = p.oy * p.ox;
+    build_bop<B>(tt, lane, bop);
     float bk = -INFINITY;
     int bi = INT_MAX;
-    for (int tile = wave; tile < tl.ntiles; tile += MF_NW) {
-        // the lane's A row (base of row n16) and its four output rows
-        int aoff[NQ], aph;
-        {
-            const int r = 16 * tile + n16, rr = r < tl.nrows ? r : 0;
-            const int xy = rr % tl.nxy, ph = rr / tl.nxy;
-            const int bx = 4 * (xy % tl.nbx), by = 4 * (xy / tl.nbx);
-            aph = ph * tl.tz;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int g = 4 * q + grp < G::NG ? 4 * q + grp : 0;
-                aoff[q] = (by + 2 * (g / G::GX)) * rp + bx + 4 * (g % G::GX);
-            }
-        }
-        // the lane's four output rows: displacement (odx, ody) relative to the
-        // valid range's corner, plane offset oph; records at orec + dz planes
-        int odx[4], ody[4], oph[4], orec[4], oxy[4];
-        bool orow[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = 16 * tile + 4 * grp + i;
-            orow[i] = r < tl.nrows;
-            const int rr = orow[i] ? r : 0;
-            const int xy = rr % tl.nxy, ph = rr / tl.nxy;
-            odx[i] = 4 * (xy % tl.nbx) + oa - px;
-            ody[i] = 4 * (xy / tl.nbx) + ob;
-            oph[i] = ph * tl.tz;
-            orow[i] = orow[i] && odx[i] >= 0 && odx[i] < dxn && ody[i] < dyn;
-            orec[i] = (wz0 * p.oy + (wy0 + min(ody[i], dyn - 1))) * p.ox +
-                      (wx0 + min(max(odx[i], 0), dxn - 1));
-            oxy[i] = (loy + ody[i] + p.w) * side + (lox + odx[i] + p.w);
-        }
-        float4v acc[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) acc[k] = float4v{0.0f, 0.0f, 0.0f, 0.0f};
-        // A operand of plane t + phase (clamped: planes past the window feed
-        // only displacements that are masked out)
-        auto load_a = [&](int t, half8 (&aop)[NQ]) {
-            const int pz = min(t + aph, ez - 1);
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const _Float16 *ap = win + pz * pl + aoff[q];
-                const half4 lo = *reinterpret_cast<const half4 *>(ap);
-                const half4 hi = *reinterpret_cast<const half4 *>(ap + rp);
-                aop[q] = half8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-            }
-        };
-        // statistics records of the four output rows, loaded one displacement
-        // plane ahead of their ranking (clamped into the valid range, so every
-        // load is in bounds; invalid ones are masked)
-        StatU16 rec0[4];
-        auto fetch = [&](int tau, StatU16 (&rec)[4]) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                rec[i] = p.stats[orec[i] + min(tau + oph[i], dzn - 1) * plane_rec];
-        };
-        // ranking of displacement plane tau, then the records of tau + 1
-        auto rank = [&](const float4v &c4, int tau) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int dz = tau + oph[i];
-                const float sts = __builtin_fmaf(fST, (float)rec0[i].s, fshift);
-                const float cov = __builtin_fmaf(fN, c4[i], -sts);
-                const bool valid = orow[i] && dz < dzn;
-                const float key = valid ? cov * rec0[i].r : -INFINITY;
-                const int idx = valid ? (loz + dz + p.w) * side2 + oxy[i] : INT_MAX;
-                keep_best(bk, bi, key, idx);
-            }
-            fetch(tau + 1, rec0);
-        };
-        fetch(0, rec0);
-        half8 aop[NQ];
-        load_a(0, aop);
-        sweep_block<B, NQ, 0>(0, acc, bop, aop, load_a, rank);
-        for (int t0 = B; t0 < tl.tz; t0 += B) sweep_block<B, NQ, 1>(t0, acc, bop, aop, load_a, rank);
-        sweep_block<B, NQ, 2>(tl.tz, acc, bop, aop, load_a, rank);
-    }
-
-    // ---- workgroup argmax
-    for (int off = 32; off > 0; off >>= 1) {
-        const float ok = __shfl_xor(bk, off);
-        const int oi = __shfl_xor(bi, off);
-        keep_best(bk, bi, ok, oi);
-    }
-    if (lane == 0) {
-        sm.key[wave] = bk;
-        sm.idx[wave] = bi;
-    }
-    __syncthreads();
-    bk = sm.key[0];
-    bi = sm.idx[0];
-#pragma unroll
-    for (int i = 1; i < MF_NW; ++i) keep_best(bk, bi, sm.key[i], sm.idx[i]);
-    if (bi == INT_MAX) {
-        if (tid == 0) put(p, blk, 0, 0, 0, NAN);
-        return;
-    }
-
-    // ---- exact NCC at the winner from the staged integers (v - c)
-    const int ddx = bi % side - p.w, ddy = (bi / side) % side - p.w, ddz = bi / (side * side) - p.w;
-    const int rx = ddx - lox + px, ry = ddy - loy, rz = ddz - loz;
-    long long sf = 0, sff = 0, stf = 0;
-    for (int o = tid; o < N; o += MF_NT) {
-        const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
-        const long long f = (long long)(float)win[(rz + oz) * pl + (ry + oy) * rp + rx + ox];
-        const long long tv = (long long)(float)tt[(oz * G::TYW + oy + OFF) * G::TXW + ox + OFF];
-        sf += f;
-        sff += f * f;
-        stf += tv * f;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        sf += __shfl_xor(sf, off);
-        sff += __shfl_xor(sff, off);
-        stf += __shfl_xor(stf, off);
-    }
-    __syncthreads();  // sm.red reused
-    if (lane == 0) {
-        sm.red[wave * 4] = sf;
-        sm.red[wave * 4 + 1] = sff;
-        sm.red[wave * 4 + 2] = stf;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        sf = sff = stf = 0;
-        for (int i = 0; i < MF_NW; ++i) {
-            sf += sm.red[i * 4];
-            sff += sm.red[i * 4 + 1];
-            stf += sm.red[i * 4 + 2];
-        }
-        const long long tc2 = stt - 2ll * c * st + (long long)N * c * c;  // sum (T - c)^2
-        const long long vt = (long long)N * tc2 - sTc * sTc;
-        const long long vf = (long long)N * sff - sf * sf;
-        const long long cv = (long long)N * stf - sTc * sf;
-        const double v = (vt > 0 && vf > 0) ? (double)cv / sqrt((double)vt * (double)vf) : 0.0;
-        put(p, blk, ddx, ddy, ddz, (float)v);
-    }
+    sweep_tiles<B, PB_NW>(p, g, win, rp, pl, bop, st - (long long)N * c, c, wave, lane, bk, bi);
+    finish_block<B, PB_NW>(p, g, blk, win, rp, pl, tt, st, stt, c, bk, bi, sm, tid);
 }
 
+// ------------------------------------------------------------------- host
 typedef void (*mf_kernel_t)(MfParams);
 
 struct MfVariant {
     int b;
     mf_kernel_t fn;
-    int tyw, txw;
+    int tt_bytes;
 };
 
-#define MFV(B) {B, k_match_mfma<B>, KGeo<B>::TYW, KGeo<B>::TXW}
+#define MFV(B) {B, k_match_mfma<B>, KGeo<B>::TT_BYTES}
 const MfVariant kMfVariants[] = {MFV(3), MFV(5), MFV(7), MFV(9)};
 #undef MFV
 
@@ -566,10 +660,10 @@ const MfVariant *mf_variant(int b) {
     return nullptr;
 }
 
-// LDS pitches for the unclipped window of (b, w): rows padded so that rows
+// LDS sizes for the unclipped window of (b, w): rows padded so that rows
 // four apart (the bases' y step) start on different banks.
 struct MfPlan {
-    int rp, pl;
+    int rp, pl;  // row and plane pitch (halves)
     size_t lds;
 };
 
@@ -585,8 +679,7 @@ bool mf_plan(int b, int w, size_t limit, MfPlan *out) {
     int pl = py * rp;
     if (((pl * 2) % 256) == 0) pl += 8;
     const int planes = d + b - 1;
-    const size_t tt = ((size_t)b * v->tyw * v->txw * 2 + 15) & ~(size_t)15;
-    const size_t lds = tt + (size_t)planes * pl * 2;
+    const size_t lds = (size_t)v->tt_bytes + (size_t)planes * pl * 2;
     if (lds + sizeof(MfSmall) > limit) return false;
     out->rp = rp;
     out->pl = pl;
@@ -612,9 +705,6 @@ hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream) {
     if (!mf_plan(a.block, a.window, device_lds_limit(), &pl) || !mfma_fits(a))
         return hipErrorInvalidValue;
     const MfVariant *v = mf_variant(a.block);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(v->fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
-    if (e != hipSuccess) return e;
     MfParams p;
     p.ref = static_cast<const uint16_t *>(a.ref);
     p.flt = static_cast<const uint16_t *>(a.flt);
@@ -622,6 +712,7 @@ hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream) {
     p.ny = a.ny;
     p.nz = a.nz;
     p.centers = a.centers;
+    p.first = 0;
     p.w = a.window;
     p.stats = static_cast<const StatU16 *>(a.stats);
     p.ox = a.ox;
@@ -631,11 +722,14 @@ hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream) {
     p.disp = a.disp;
     p.ncc = a.ncc;
     p.conf = a.conf;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(v->fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
+    if (e != hipSuccess) return e;
     const int64_t chunk = 1ll << 30;
     for (int64_t first = 0; first < a.n; first += chunk) {
         p.first = first;
         const int64_t cnt = a.n - first < chunk ? a.n - first : chunk;
-        hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(MF_NT), pl.lds, stream, p);
+        hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(64 * PB_NW), pl.lds, stream, p);
     }
     return hipGetLastError();
 }

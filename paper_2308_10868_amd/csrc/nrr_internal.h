@@ -164,6 +164,8 @@ hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nse
 struct TileShape {
     int32_t arith, rx, ry, nt, pf, cz;
 };
+// Arithmetic form launch_match would use now (0 dot2, 1 FMA, 2 MFMA).
+int match_arith(nrr_dtype dtype, const MatchArgs &a);
 // `shape` (optional) forces the shape; else env overrides, tuned table, cost model.
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
                         const TileShape *shape = nullptr);

@@ -52,7 +52,7 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_traffic_records_are_well_formed():
-    for wl, (name, sources) in bench.TRAFFIC_FILES.items():
+    for (wl, arith), (name, sources) in bench.TRAFFIC_FILES.items():
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
         assert t["workload"] == wl and t["sources"] == sources
@@ -61,6 +61,6 @@ def test_traffic_records_are_well_formed():
         assert abs(t["traffic_bytes"] - scaled) <= 1e-4 * scaled
         # the scales come from the 256 MiB copy calibration
         assert abs(t["fetch_scale"] - 262144.0 / t["copy_256mib_fetch_kib"]) < 1e-3
-        got = bench.measured_traffic(wl)
+        got = bench.measured_traffic(wl, arith)
         assert got is None or got == t["traffic_bytes"]
-    assert bench.measured_traffic("no_such_workload") is None
+    assert bench.measured_traffic("no_such_workload", "dot2") is None
