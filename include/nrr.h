@@ -128,6 +128,24 @@ nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dim
                              int64_t capacity, int64_t *k_out, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/* nrr_select_blocks for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results without `workspace`; the
+ * scratch comes from a 32 MiB array of this library that each GPU it runs
+ * on holds until the process ends (its device address is looked up once per
+ * device, on the first call with that device current).  No allocation, no
+ * hipMemset: the selection writes every scratch word before reading it.
+ *
+ * Calls that overlap on one GPU (concurrent streams, or host threads
+ * sharing a device) share that array and race: serialise them.  Errors as
+ * nrr_select_blocks, plus UNSUPPORTED when nrr_select_workspace_bytes for
+ * these sizes exceeds 32 MiB (about 4.19 million candidate blocks) or the
+ * device index is 64 or more, HIP if the array's address cannot be found. */
+nrr_status nrr_select_blocks_static(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                    int32_t block, int32_t stride, double fraction,
+                                    int32_t *centers, int64_t capacity, int64_t *k_out,
+                                    void *stream);
+
 /* Selection variants of the same paragraph: candidates restricted to a
  * region, and a connectivity pattern that keeps selected blocks apart.
  *

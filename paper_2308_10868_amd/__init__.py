@@ -132,6 +132,7 @@ def load():
         "nrr_block_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, P]),
         "nrr_select_blocks_ex": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I32, P, I64, P, P, SZ,
                                       P]),
+        "nrr_select_blocks_static": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P]),
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnrr.so")
 SOURCES = ["api.cpp", "server.cpp", "select.hip", "stats.hip", "match.hip", "match_aniso.hip",
-           "match_mfma.hip"]
+           "match_mfma.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

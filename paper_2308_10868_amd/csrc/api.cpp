@@ -31,6 +31,19 @@ nrr_status ok() {
     return NRR_OK;
 }
 
+}  // namespace
+
+// The thread-local detail of nrr_last_error, for the library's other files.
+nrr_status nrr::set_error(nrr_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+namespace {
+
 nrr_status check_grid(const int32_t dims[3], int32_t block, int32_t stride, int32_t grid[3]) {
     if (!dims) return fail(NRR_ERR_INVALID_ARG, "dims is NULL");
     if (block < 3 || block % 2 == 0)

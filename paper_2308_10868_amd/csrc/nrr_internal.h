@@ -11,6 +11,9 @@
 
 namespace nrr {
 
+// Records the detail nrr_last_error returns (printf format); returns s.
+nrr_status set_error(nrr_status s, const char *fmt, ...);
+
 // ------------------------------------------------------------- selection
 // Workspace of the selection: one 64-bit ranking key per candidate block,
 // the radix-select state and per-tile counts for the ordered compaction.
