@@ -338,7 +338,7 @@ def main() -> int:
     lat = np.array(lat)
 
     achieved = OPS_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
-    arith = nrr.match_arith(dt_code, dims, b, w)
+    arith = nrr.match_plan(dt_code, dims, b, w)["form"]
     if arith == "mfma":
         # fp16 matrix-core products of exact 12-bit offsets: judged against
         # the fp16 MFMA peak, with the FP32-vector fraction beside it

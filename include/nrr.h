@@ -94,17 +94,6 @@ nrr_status nrr_match_workspace_bytes(nrr_dtype dtype, const int32_t dims[3], int
  * not fit in LDS), INVALID_ARG for malformed values. */
 nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window);
 
-/* Arithmetic form of the cross term that nrr_block_match would launch now
- * for these arguments on the current device (host-only, no device work):
- * *arith = 0 exact int16 dot2 (12-bit data), 1 FP32 FMA, 2 fp16 matrix-core
- * products of exact 12-bit offsets with FP32 sums (12-bit data, block edges
- * 3-9, the window in LDS; the default where it serves).  The NRR_ARITH
- * environment override (dot2 | fma | mfma) and shapes chosen by
- * nrr_tune_match are taken into account.  Errors as nrr_match_supported;
- * INVALID_ARG for NULL pointers. */
-nrr_status nrr_match_arith(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
-                           int32_t *arith);
-
 /* ---------------------------------------------------------------- selection
  * Variance-ranked block selection ("Parallel feature selection" paragraph:
  * each candidate block's intensity variance is computed, the candidates are
@@ -292,7 +281,8 @@ nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int3
  * every later search in this process with that (dtype, block, window):
  * nrr_block_match, nrr_block_match_prepared and the batched search.
  *
- *  A shape: arith 0 = dot2 (12-bit data), 1 = FMA; rx x ry displacements
+ *  A shape: arith 0 = dot2 (12-bit data), 1 = FMA, 2 = fp16 matrix cores
+ *  (12-bit data, see nrr_match_plan); rx x ry displacements
  *  per thread; nt threads; pf 1 = records prefetched; cz displacement planes
  *  staged at once (0 in requests: as planned).
  *
@@ -317,6 +307,36 @@ nrr_status nrr_tune_match(const void *ref, const void *flt, nrr_dtype dtype,
  * forgetting every tuned shape.  Host only. */
 nrr_status nrr_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window, nrr_tile_shape *out);
 nrr_status nrr_clear_tuning(void);
+
+/* Host-only views of the shape choice (no device work).
+ *
+ * nrr_match_plan: the shape nrr_block_match would launch now for these
+ * arguments on the current device, with the NRR_ARITH (dot2 | fma | mfma)
+ * and NRR_TILE overrides and tuned shapes taken into account.  arith 2 is
+ * the fp16 matrix-core form (12-bit data, block edges 3-9, the window in
+ * LDS; the default where it serves): products of exact 12-bit offsets with
+ * FP32 sums, 256 threads; its rx, ry are 0 and pf -1.
+ *
+ * nrr_match_shapes: the compiled shapes nrr_tune_match times for (dtype,
+ * block, window), each with a z-chunk cz; *count receives how many there are
+ * (at most cap written to out).
+ *
+ * nrr_set_tuned_shape: pins `shape` for every later search of (dtype,
+ * block, window) in this process, as nrr_tune_match does with the fastest;
+ * cz 0 = as planned, else a cap on the z-chunk.  UNSUPPORTED if the shape is
+ * not compiled for that block size (a shape of the batched search is
+ * accepted and used there).
+ *
+ * nrr_batch_shapes: the shape each parameter set of a batched plan over
+ * `sets` would run with (out[nsets]); errors as nrr_batch_layout.
+ *
+ * Errors: as nrr_match_supported, INVALID_ARG for NULL pointers. */
+nrr_status nrr_match_plan(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
+                          nrr_tile_shape *shape);
+nrr_status nrr_match_shapes(nrr_dtype dtype, int32_t block, int32_t window, nrr_tile_shape *out,
+                            int32_t cap, int32_t *count);
+nrr_status nrr_set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window,
+                               const nrr_tile_shape *shape);
 
 /* ----------------------------------------------------------- batched search
  * The paper's intra-operative parametric search (block size, window and
@@ -357,6 +377,8 @@ typedef struct nrr_batch_plan nrr_batch_plan;
 
 nrr_status nrr_batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
                             int32_t nsets, int64_t *offsets, size_t *workspace_bytes);
+nrr_status nrr_batch_shapes(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
+                            int32_t nsets, nrr_tile_shape *out);
 
 nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dtype,
                                  const int32_t dims[3], const nrr_param_set *sets, int32_t nsets,

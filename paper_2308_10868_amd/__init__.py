@@ -127,7 +127,10 @@ def load():
         "nrr_select_workspace_bytes": (st, [P, I32, I32, P]),
         "nrr_match_workspace_bytes": (st, [ctypes.c_int, P, I32, P]),
         "nrr_match_supported": (st, [ctypes.c_int, I32, I32]),
-        "nrr_match_arith": (st, [ctypes.c_int, P, I32, I32, P]),
+        "nrr_match_plan": (st, [ctypes.c_int, P, I32, I32, P]),
+        "nrr_match_shapes": (st, [ctypes.c_int, I32, I32, P, I32, P]),
+        "nrr_set_tuned_shape": (st, [ctypes.c_int, I32, I32, P]),
+        "nrr_batch_shapes": (st, [ctypes.c_int, P, P, I32, P]),
         "nrr_select_blocks": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P, SZ, P]),
         "nrr_block_match": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ, P]),
         "nrr_select_blocks_ex": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I32, P, I64, P, P, SZ,
@@ -215,13 +218,29 @@ def match_supported(dtype: int, block: int, window: int) -> bool:
 ARITH_NAMES = {0: "dot2", 1: "fma", 2: "mfma"}
 
 
-def match_arith(dtype: int, dims, block: int, window: int) -> str:
-    """Arithmetic form of the cross term nrr_block_match would launch now:
-    'dot2', 'fma' or 'mfma' (environment override and tuned shapes included)."""
+def match_plan(dtype: int, dims, block: int, window: int) -> dict:
+    """The shape nrr_block_match would launch now (environment overrides and
+    tuned shapes included), as a dict with 'form' = 'dot2', 'fma' or 'mfma'."""
+    out = TileShape()
+    _check(load().nrr_match_plan(dtype, _dims3(dims), block, window, ctypes.byref(out)))
+    d = out.as_dict()
+    d["form"] = ARITH_NAMES.get(d["arith"], str(d["arith"]))
+    return d
+
+
+def match_shapes(dtype: int, block: int, window: int) -> list:
+    """The compiled shapes the tuner times for (dtype, block, window)."""
     lib = load()
-    a = ctypes.c_int32(-1)
-    _check(lib.nrr_match_arith(dtype, _dims3(dims), block, window, ctypes.byref(a)))
-    return ARITH_NAMES.get(a.value, str(a.value))
+    arr = (TileShape * 64)()
+    n = ctypes.c_int32()
+    _check(lib.nrr_match_shapes(dtype, block, window, arr, 64, ctypes.byref(n)))
+    return [arr[i].as_dict() for i in range(min(n.value, 64))]
+
+
+def set_tuned_shape(dtype: int, block: int, window: int, shape: dict):
+    """Pin a compiled shape for later searches of (dtype, block, window)."""
+    t = TileShape(*[int(shape.get(k, 0)) for k, _ in TileShape._fields_])
+    _check(load().nrr_set_tuned_shape(dtype, block, window, ctypes.byref(t)))
 
 
 def _torch():
@@ -513,6 +532,14 @@ def batch_layout(dtype: int, dims, sets):
     nb = ctypes.c_size_t()
     _check(load().nrr_batch_layout(dtype, _dims3(dims), arr, len(sets), offs, ctypes.byref(nb)))
     return list(offs), nb.value
+
+
+def batch_shapes(dtype: int, dims, sets) -> list:
+    """The shape each parameter set of a batched plan would run with."""
+    arr = _param_array(sets)
+    out = (TileShape * max(len(sets), 1))()
+    _check(load().nrr_batch_shapes(dtype, _dims3(dims), arr, len(sets), out))
+    return [out[i].as_dict() for i in range(len(sets))]
 
 
 class BatchPlan:

@@ -149,9 +149,9 @@ nrr_status nrr_match_supported(nrr_dtype dtype, int32_t block, int32_t window) {
     return ok();
 }
 
-nrr_status nrr_match_arith(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
-                           int32_t *arith) {
-    if (!dims || !arith) return fail(NRR_ERR_INVALID_ARG, "dims and arith must be non-NULL");
+nrr_status nrr_match_plan(nrr_dtype dtype, const int32_t dims[3], int32_t block, int32_t window,
+                          nrr_tile_shape *shape) {
+    if (!dims || !shape) return fail(NRR_ERR_INVALID_ARG, "dims and shape must be non-NULL");
     nrr_status s = nrr_match_supported(dtype, block, window);
     if (s != NRR_OK) return s;
     int32_t g[3];
@@ -164,7 +164,10 @@ nrr_status nrr_match_arith(nrr_dtype dtype, const int32_t dims[3], int32_t block
     a.window = window;
     a.ox = dims[0] - block + 1;
     a.oy = dims[1] - block + 1;
-    *arith = nrr::match_arith(dtype, a);
+    nrr::TileShape t;
+    if (!nrr::match_plan(dtype, a, &t))
+        return fail(NRR_ERR_UNSUPPORTED, "no compiled shape for block %d window %d", block, window);
+    *shape = nrr_tile_shape{t.arith, t.rx, t.ry, t.nt, t.pf, t.cz};
     return ok();
 }
 
@@ -686,6 +689,37 @@ nrr_status nrr_clear_tuning(void) {
     return ok();
 }
 
+nrr_status nrr_match_shapes(nrr_dtype dtype, int32_t block, int32_t window, nrr_tile_shape *out,
+                            int32_t cap, int32_t *count) {
+    if (!count || (cap > 0 && !out))
+        return fail(NRR_ERR_INVALID_ARG, "count (and out when cap > 0) must be non-NULL");
+    nrr_status s = nrr_match_supported(dtype, block, window);
+    if (s != NRR_OK) return s;
+    nrr::TileShape shapes[64];
+    const int ns = nrr::match_shapes(dtype, block, window, shapes, 64);
+    for (int i = 0; i < ns && i < cap; ++i) {
+        const nrr::TileShape &t = shapes[i];
+        out[i] = nrr_tile_shape{t.arith, t.rx, t.ry, t.nt, t.pf, t.cz};
+    }
+    *count = ns;
+    return ok();
+}
+
+nrr_status nrr_set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window,
+                               const nrr_tile_shape *shape) {
+    if (!shape) return fail(NRR_ERR_INVALID_ARG, "shape is NULL");
+    nrr_status s = nrr_match_supported(dtype, block, window);
+    if (s != NRR_OK) return s;
+    const nrr::TileShape t{shape->arith, shape->rx, shape->ry, shape->nt, shape->pf, shape->cz};
+    if (t.cz < 0) return fail(NRR_ERR_INVALID_ARG, "cz must be >= 0 (got %d)", t.cz);
+    if (!nrr::shape_known(dtype, block, window, t))
+        return fail(NRR_ERR_UNSUPPORTED,
+                    "shape (arith %d, %dx%d, %d threads, pf %d) is not compiled for block %d "
+                    "window %d", t.arith, t.rx, t.ry, t.nt, t.pf, block, window);
+    nrr::set_tuned_shape(dtype, block, window, t);
+    return ok();
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------- batched search
@@ -732,6 +766,21 @@ nrr_status nrr_batch_layout(nrr_dtype dtype, const int32_t dims[3], const nrr_pa
     if (s != NRR_OK) return s;
     if (offsets) std::copy(L.off.begin(), L.off.end(), offsets);
     if (workspace_bytes) *workspace_bytes = L.total;
+    return ok();
+}
+
+nrr_status nrr_batch_shapes(nrr_dtype dtype, const int32_t dims[3], const nrr_param_set *sets,
+                            int32_t nsets, nrr_tile_shape *out) {
+    BatchLayout L;
+    nrr_status s = batch_layout(dtype, dims, sets, nsets, &L);
+    if (s != NRR_OK) return s;
+    if (nsets > 0 && !out) return fail(NRR_ERR_INVALID_ARG, "out is NULL");
+    for (int32_t i = 0; i < nsets; ++i) {
+        nrr::TileShape t;
+        if (!nrr::batch_variant_shape(dtype, L.variant[i], L.cz[i], &t))
+            return fail(NRR_ERR_UNSUPPORTED, "set %d: no batched shape", i);
+        out[i] = nrr_tile_shape{t.arith, t.rx, t.ry, t.nt, t.pf, t.cz};
+    }
     return ok();
 }
 

@@ -1219,11 +1219,44 @@ int match_shapes(nrr_dtype dtype, int32_t block, int32_t window, TileShape *out,
     return n < cap ? n : cap;
 }
 
-int match_arith(nrr_dtype dtype, const MatchArgs &a) {
-    if (mfma_fits(a) && wants_mfma(dtype, a.block, a.window, nullptr)) return kArithMfma;
+bool match_plan(nrr_dtype dtype, const MatchArgs &a, TileShape *out) {
+    if (mfma_fits(a) && wants_mfma(dtype, a.block, a.window, nullptr)) {
+        *out = TileShape{kArithMfma, 0, 0, 256, -1, 0};
+        return true;
+    }
     Plan pl;
-    if (!choose(dtype, a.block, a.window, device_lds_limit(), nullptr, &pl)) return -1;
-    return pl.v->arith;
+    if (!choose(dtype, a.block, a.window, device_lds_limit(), nullptr, &pl)) return false;
+    *out = TileShape{pl.v->arith, pl.v->rx, pl.v->ry, pl.v->nt, pl.v->pf, pl.cz};
+    return true;
+}
+
+bool shape_known(nrr_dtype dtype, int32_t block, int32_t window, const TileShape &sh) {
+    if (sh.arith == kArithMfma) return mfma_supported(dtype, block, window);
+    const size_t limit = device_lds_limit();
+    for (const Variant &v : kVariants)
+        if (v.dtype == dtype && v.b == block && v.arith == sh.arith && v.rx == sh.rx &&
+            v.ry == sh.ry && v.nt == sh.nt && v.pf == sh.pf) {
+            Plan pl;
+            if (plan_variant(v, window, limit, limit / 2, &pl)) return true;
+        }
+    const Variant *tab = dtype == NRR_F32 ? kBatchF32 : kBatchU16;
+    const int nv = dtype == NRR_F32 ? (int)(sizeof(kBatchF32) / sizeof(Variant))
+                                    : (int)(sizeof(kBatchU16) / sizeof(Variant));
+    for (int i = 0; i < nv; ++i)
+        if (tab[i].b == block && tab[i].arith == sh.arith && tab[i].rx == sh.rx &&
+            tab[i].ry == sh.ry && tab[i].nt == sh.nt && tab[i].pf == sh.pf)
+            return true;
+    return false;
+}
+
+bool batch_variant_shape(nrr_dtype dtype, int32_t variant, int32_t cz, TileShape *out) {
+    const Variant *tab = dtype == NRR_F32 ? kBatchF32 : kBatchU16;
+    const int nv = dtype == NRR_F32 ? (int)(sizeof(kBatchF32) / sizeof(Variant))
+                                    : (int)(sizeof(kBatchU16) / sizeof(Variant));
+    if (variant < 0 || variant >= nv) return false;
+    const Variant &v = tab[variant];
+    *out = TileShape{v.arith, v.rx, v.ry, v.nt, v.pf, cz};
+    return true;
 }
 
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,

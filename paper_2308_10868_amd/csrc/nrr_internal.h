@@ -167,8 +167,14 @@ hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nse
 struct TileShape {
     int32_t arith, rx, ry, nt, pf, cz;
 };
-// Arithmetic form launch_match would use now (0 dot2, 1 FMA, 2 MFMA).
-int match_arith(nrr_dtype dtype, const MatchArgs &a);
+// The shape launch_match would use now (arith 0 dot2, 1 FMA, 2 MFMA); false
+// when no compiled shape serves.
+bool match_plan(nrr_dtype dtype, const MatchArgs &a, TileShape *out);
+// Whether `sh` (cz ignored) is a compiled plain or batched shape for
+// (dtype, block, window).
+bool shape_known(nrr_dtype dtype, int32_t block, int32_t window, const TileShape &sh);
+// The shape of a batched set planned as `variant` with z-chunk cz.
+bool batch_variant_shape(nrr_dtype dtype, int32_t variant, int32_t cz, TileShape *out);
 // `shape` (optional) forces the shape; else env overrides, tuned table, cost model.
 hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
                         const TileShape *shape = nullptr);

@@ -104,6 +104,30 @@ def test_batch_f32_config_sets_equal_plain_calls(torch_dev, c1):
     plan.close()
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_f32_config_sets_match_oracle_per_set(torch_dev, c1, use_graph):
+    """The 32 parameter sets of the batched workload (64^3 float pair, block
+    {5,7,9}, window {5,8,12}, fraction {0.05..0.5}, stride = block), each set
+    against the oracle: bit-exact selection, the parity rule for the search;
+    eager and graph-replayed (the graph plan checked on two replays)."""
+    torch = torch_dev
+    sets = synth.gen_param_sets(32, seed=1)
+    say("batch f32 32 sets vs oracle, graph" if use_graph else "batch f32 32 sets vs oracle")
+    plan = run_plan(torch, to_dev(c1.ref), to_dev(c1.flt), sets, use_graph=use_graph)
+    for rep in range(2 if use_graph else 1):
+        if rep:
+            plan.ncc.fill_(-7.0)  # stale values must not survive the replay
+            plan.run()
+            torch.cuda.synchronize()
+        for i, (q, (c, d, n, cf)) in enumerate(zip(sets, plan.results())):
+            b, w, stride, frac = q
+            c_o, _ = oracle.select(c1.ref, b, stride, frac)
+            assert np.array_equal(to_host(c), c_o), (rep, i, q)
+            check_match(c1.ref, c1.flt, c_o, b, w, to_host(d), to_host(n), to_host(cf),
+                        label="rep%d set%d" % (rep, i))
+    plan.close()
+
+
 def test_batch_u16_equals_plain_and_oracle(torch_dev, u16_pair, monkeypatch):
     torch = torch_dev
     monkeypatch.setenv("NRR_ARITH", "dot2")
