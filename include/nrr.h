@@ -466,6 +466,29 @@ const char *nrr_status_string(nrr_status s);
  * ("" if none).  Valid until the next call on the same thread. */
 const char *nrr_last_error(void);
 
+/* The search of nrr_block_match (window statistics included) that also
+ * writes the NCC its ranking arithmetic gives every valid displacement: the
+ * ranking key N cov / sqrt(N varF) of the NCC equation (section 3) divided
+ * by sqrt(N varT), for checking that arithmetic's error against an exact
+ * reference per displacement.  Diagnostic; slower than nrr_block_match.
+ *
+ *  arith      -1: the form nrr_block_match would use (see nrr_match_plan);
+ *             0 dot2, 1 FMA, 2 fp16 matrix cores (each where compiled for
+ *             this dtype and block edge, else UNSUPPORTED).
+ *  surface    device, float [n][2W+1][2W+1][2W+1], indexed by the shift
+ *             index ((dz+W)(2W+1) + (dy+W))(2W+1) + (dx+W); NaN for
+ *             displacements whose block leaves the volume and for blocks
+ *             outside the volume or flat (every NCC 0 by definition).
+ *  others     as nrr_block_match (disp, ncc, conf written as it writes them).
+ *
+ * Errors as nrr_block_match, INVALID_ARG for a NULL surface or arith out of
+ * range. */
+nrr_status nrr_block_match_surface(const void *ref, const void *flt, nrr_dtype dtype,
+                                   const int32_t dims[3], const int32_t *centers, int64_t n,
+                                   int32_t block, int32_t window, int32_t arith, int32_t *disp,
+                                   float *ncc, float *conf, float *surface, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
 /* ABI version (major*10000 + minor*100 + patch). */
 int32_t nrr_version(void);
 

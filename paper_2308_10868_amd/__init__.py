@@ -128,6 +128,8 @@ def load():
         "nrr_match_workspace_bytes": (st, [ctypes.c_int, P, I32, P]),
         "nrr_match_supported": (st, [ctypes.c_int, I32, I32]),
         "nrr_match_plan": (st, [ctypes.c_int, P, I32, I32, P]),
+        "nrr_block_match_surface": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, I32, P, P, P,
+                                         P, P, SZ, P]),
         "nrr_match_shapes": (st, [ctypes.c_int, I32, I32, P, I32, P]),
         "nrr_set_tuned_shape": (st, [ctypes.c_int, I32, I32, P]),
         "nrr_batch_shapes": (st, [ctypes.c_int, P, P, I32, P]),
@@ -368,6 +370,32 @@ def block_match(ref, flt, centers, block: int, window: int, workspace=None, out=
                                ctypes.c_void_p(ncc.data_ptr()), ctypes.c_void_p(conf.data_ptr()),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
     return disp, ncc, conf
+
+
+def block_match_surface(ref, flt, centers, block: int, window: int, arith: str = "default"):
+    """The search plus the ranking NCC of every valid displacement:
+    (disp, ncc, conf, surface[n, 2W+1, 2W+1, 2W+1] indexed [dz][dy][dx], NaN
+    where a displacement is invalid).  arith: 'default', 'dot2', 'fma' or
+    'mfma'.  A diagnostic of the ranking arithmetic."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    n = centers.shape[0]
+    side = 2 * window + 1
+    dev = ref.device
+    disp = torch.empty((max(n, 1), 3), dtype=torch.int32, device=dev)
+    ncc = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    conf = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    surf = torch.empty((max(n, 1), side, side, side), dtype=torch.float32, device=dev)
+    ws = _workspace(match_workspace_bytes(dt, dims, block), dev, None)
+    code = {"default": -1, "dot2": 0, "fma": 1, "mfma": 2}[arith]
+    _check(lib.nrr_block_match_surface(
+        ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
+        ctypes.c_void_p(centers.data_ptr()), n, block, window, code,
+        ctypes.c_void_p(disp.data_ptr()), ctypes.c_void_p(ncc.data_ptr()),
+        ctypes.c_void_p(conf.data_ptr()), ctypes.c_void_p(surf.data_ptr()),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(ref)))
+    return disp[:n], ncc[:n], conf[:n], surf[:n]
 
 
 def _triple(v) -> ctypes.Array:

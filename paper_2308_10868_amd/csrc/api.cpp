@@ -419,6 +419,39 @@ nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
                      L, st);
 }
 
+nrr_status nrr_block_match_surface(const void *ref, const void *flt, nrr_dtype dtype,
+                                   const int32_t dims[3], const int32_t *centers, int64_t n,
+                                   int32_t block, int32_t window, int32_t arith, int32_t *disp,
+                                   float *ncc, float *conf, float *surface, void *workspace,
+                                   size_t workspace_bytes, void *stream) {
+    nrr::StatsLayout L;
+    nrr_status s = check_match(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf,
+                               workspace, workspace_bytes, &L);
+    if (s != NRR_OK || n == 0) return s;
+    if (!surface) return fail(NRR_ERR_INVALID_ARG, "surface is NULL");
+    if (arith < -1 || arith > 2) return fail(NRR_ERR_INVALID_ARG, "arith must be -1..2");
+    const nrr::MatchArgs a =
+        match_args(ref, flt, dims, centers, n, block, window, disp, ncc, conf, workspace, L);
+    if (arith < 0) {
+        nrr::TileShape t;
+        if (!nrr::match_plan(dtype, a, &t))
+            return fail(NRR_ERR_UNSUPPORTED, "no compiled shape for block %d window %d", block,
+                        window);
+        arith = t.arith;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t side = 2 * (int64_t)window + 1;
+    hipError_t e = nrr::launch_fill(surface, n * side * side * side, NAN, st);
+    if (e != hipSuccess) return hip_status(e, "surface fill");
+    if ((e = nrr::launch_stats(flt, dtype, dims, block, workspace, st)) != hipSuccess)
+        return hip_status(e, "window statistics launch");
+    e = nrr::launch_match_surface(dtype, arith, a, surface, st);
+    if (e == hipErrorNotSupported)
+        return fail(NRR_ERR_UNSUPPORTED, "no surface form %d for block %d window %d", arith, block,
+                    window);
+    return hip_status(e, "surface search launch");
+}
+
 // ------------------------------------------------------- per-axis sizes
 
 namespace {

@@ -20,7 +20,9 @@
 //        by v_dot2_i32_i16; the block's planes are grouped so no int32 partial
 //        sum can overflow (|T'|, |F'| <= 2048);
 //      FMA (any data): T^ = T - mean(T) in FP32 against F - c (c = the
-//        block mean, rounded to an integer for 12-bit data) with v_fmac_f32;
+//        block mean, rounded to an integer for 12-bit data) with v_fmac_f32,
+//        summed in FP32 per block plane, then across planes (FP64 for 12-bit
+//        data);
 //  * the window statistics (sum F and 1/sqrt of its spread) come from a
 //    per-voxel table computed once per call (stats.hip), so the epilogue per
 //    displacement is a handful of operations;
@@ -73,6 +75,7 @@ struct Params {
     int32_t *disp;
     float *ncc;
     float *conf;
+    float *surface;  // optional ranking NCC per displacement (diagnostic instantiations)
 };
 
 // Workgroup index -> block index such that consecutive blocks (overlapping
@@ -446,10 +449,12 @@ __device__ __attribute__((always_inline)) inline void dot2_cross(
 // smallest shift index (irow + j*side + i).  Displacements past the valid
 // extents (nvx, nvy) are masked without a branch.  For 12-bit data the staged
 // F sums are offset by `fshift` from the table's.
-template <bool U16, bool SHIFT, int RX, int RY, typename Rec, typename XT, typename KeyT>
+template <bool U16, bool SHIFT, int RX, int RY, typename Rec, typename XT, typename KeyT,
+          bool SURF = false>
 __device__ __attribute__((always_inline)) inline void rank_tile(
     const Rec (&rec)[RX][RY], const XT (&xacc)[RX][RY], double dN, double tsum, double fshift,
-    float c, int nvx, int nvy, int irow, int side, KeyT &tk, int &ti) {
+    float c, int nvx, int nvy, int irow, int side, KeyT &tk, int &ti, float *surf = nullptr,
+    double inv_vt = 0.0) {
 #pragma unroll
     for (int j = 0; j < RY; ++j)
 #pragma unroll
@@ -468,6 +473,8 @@ __device__ __attribute__((always_inline)) inline void rank_tile(
             const bool take = valid && key > tk;  // ties keep the smaller index
             tk = take ? key : tk;
             ti = take ? irow + j * side + i : ti;
+            if constexpr (SURF)  // NCC = key / sqrt(N varT)
+                if (valid) surf[irow + j * side + i] = (float)((double)key * inv_vt);
         }
 }
 
@@ -483,7 +490,7 @@ struct Small {
 // the per-block kernel and the batched kernel.  Every thread of the NT-wide
 // workgroup calls it; it ends with all LDS reads done by the thread itself,
 // so a caller that reuses LDS for another block synchronises first.
-template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
+template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF, bool SURF = false>
 __device__ __attribute__((always_inline)) inline void match_one(const Params &p, int64_t blk,
                                                                 unsigned char *lds, Small &sm) {
     constexpr bool U16 = sizeof(Vox) == 2;
@@ -541,6 +548,7 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
     };
     long long st[2] = {0, 0};  // 12-bit: exact sums of T and T^2
     double tmean;
+    double vtn = 0.0;  // N sum T^2 - (sum T)^2 of the T actually used (surface output)
     long long sT = 0;   // DOT2: sum (T - 2048)
     double sTc = 0.0;   // FMA: sum of the centred float T^ actually used
     float c = 0.0f;     // FMA: F is staged as F - c
@@ -569,6 +577,7 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
         }
         tmean = (double)st[0] / (double)N;
         sT = st[0] - 2048ll * N;
+        vtn = (double)((long long)N * st[1] - st[0] * st[0]);
     } else {
         double sd[1] = {0.0};
         for (int o = tid; o < N; o += NT) {
@@ -599,6 +608,7 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
         stage_chunk(0, min(p.cz, g.dz) + B - 1, c);
         wg_sum<NT, double, 2>(ctr, s_redd);  // barrier publishes tp and the window
         sTc = ctr[0];
+        vtn = (double)N * ctr[1] - ctr[0] * ctr[0];
         if (!(ctr[1] > 0.0)) {  // flat block
             if (tid == 0) write_result(p, blk, g.lox, g.loy, g.loz, 0.0f);
             return;
@@ -660,9 +670,16 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
             if constexpr (PF) load_recs();
             // cross term of each displacement of the tile, kept in the narrowest
             // exact type (converted to FP64 per displacement in the ranking)
+            // FMA (B >= 5): FP32 sums of one block plane at a time, carried
+            // across planes in FP64 for 12-bit data and in a second FP32 sum
+            // for float data, so no running sum takes more than B^2 roundings
+            // at its own size: where a window's local level lies far from the
+            // block's (F - c large, varF small) a whole-block FP32 sum ranks
+            // with about 4x the error
+            constexpr bool FLUSH = ARITH == FMA && B >= 5;
             using XT = typename std::conditional<
                 ARITH == DOT2, typename std::conditional<NG == 1, int, double>::type,
-                float>::type;
+                typename std::conditional<FLUSH && U16, double, float>::type>::type;
             XT xacc[RX][RY];
             if constexpr (ARITH == DOT2) {
                 dot2_cross<B, RX, RY>(tp, base, (zc0 + dzl) % R, R, plane, pitch, xacc);
@@ -671,7 +688,10 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
 #pragma unroll
                 for (int i = 0; i < RX; ++i)
 #pragma unroll
-                    for (int j = 0; j < RY; ++j) acc[i][j] = 0.0f;
+                    for (int j = 0; j < RY; ++j) {
+                        acc[i][j] = 0.0f;
+                        xacc[i][j] = 0;
+                    }
                 for (int oz = 0; oz < B; ++oz) {
                     float tq[B][B];
                     const uint32_t *tpz = tp + oz * B * BP;
@@ -703,11 +723,22 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
                                     acc[i][j] = __builtin_fmaf(f[i + ox], tq[oy][ox], acc[i][j]);
                         }
                     }
+                    if constexpr (FLUSH) {
+#pragma unroll
+                        for (int i = 0; i < RX; ++i)
+#pragma unroll
+                            for (int j = 0; j < RY; ++j) {
+                                xacc[i][j] += (XT)acc[i][j];
+                                acc[i][j] = 0.0f;
+                            }
+                    }
                 }
+                if constexpr (!FLUSH) {
 #pragma unroll
-                for (int i = 0; i < RX; ++i)
+                    for (int i = 0; i < RX; ++i)
 #pragma unroll
-                    for (int j = 0; j < RY; ++j) xacc[i][j] = acc[i][j];
+                        for (int j = 0; j < RY; ++j) xacc[i][j] = acc[i][j];
+                }
             }
             // ---- rank the tile's displacements: key = N*cov * rsqrt(N*varF);
             // invalid displacements are masked, no branch per displacement
@@ -719,8 +750,13 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
             const double tsum = ARITH == DOT2 ? (double)sT : sTc;  // sum of the staged T
             KeyT tk = -INFINITY;
             int ti = INT_MAX;
-            rank_tile<U16, ARITH != DOT2>(rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX, g.dy - ty * RY, irow,
-                           side, tk, ti);
+            if constexpr (SURF)
+                rank_tile<U16, ARITH != DOT2, RX, RY, Rec, XT, KeyT, true>(
+                    rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX, g.dy - ty * RY, irow, side, tk,
+                    ti, p.surface + blk * side * side * side, 1.0 / sqrt(vtn));
+            else
+                rank_tile<U16, ARITH != DOT2>(rec, xacc, dN, tsum, fshift, c, g.dx - tx * RX,
+                                              g.dy - ty * RY, irow, side, tk, ti);
             better(bk, bi, tk, ti);
         }
     }
@@ -811,6 +847,16 @@ __global__ __launch_bounds__(NT) void k_match(Params p) {
                                              sm);
 }
 
+// The same search also writing the ranking NCC of every valid displacement
+// to p.surface (a diagnostic of the ranking arithmetic's error).
+template <typename Vox, int ARITH, int B, int RX, int RY, int NT, bool PF>
+__global__ __launch_bounds__(NT) void k_match_surf(Params p) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ Small sm;
+    match_one<Vox, ARITH, B, RX, RY, NT, PF, true>(
+        p, p.first + xcd_block(blockIdx.x, gridDim.x), lds, sm);
+}
+
 
 // ------------------------------------------------------------ batched search
 //
@@ -850,6 +896,7 @@ __global__ __launch_bounds__(256) void k_match_batch(const BatchSet *__restrict_
         p.disp = S.a.disp;
         p.ncc = S.a.ncc;
         p.conf = S.a.conf;
+        p.surface = nullptr;
         const int64_t blk = it - S.first_item;
         if constexpr (sizeof(Vox) == 4) {
 #define CASE_F32(ID, B, RX, RY, PF) \
@@ -1287,6 +1334,7 @@ hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
     p.disp = a.disp;
     p.ncc = a.ncc;
     p.conf = a.conf;
+    p.surface = nullptr;
     const int64_t chunk = 1ll << 30;
     for (int64_t first = 0; first < a.n; first += chunk) {
         p.first = first;
@@ -1294,6 +1342,85 @@ hipError_t launch_match(nrr_dtype dtype, const MatchArgs &a, hipStream_t stream,
         hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(v->nt), pl.lds, stream, p);
     }
     return hipGetLastError();
+}
+
+namespace {
+__global__ void k_fill(float *p, int64_t n, float v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+}  // namespace
+
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+namespace {
+// Surface-writing instantiations: one shape per (dtype, form, block edge).
+#define S16D(B, RX, RY, NT, PF) \
+    {NRR_U16, DOT2, B, RX, RY, NT, PF, k_match_surf<uint16_t, DOT2, B, RX, RY, NT, PF>}
+#define S16F(B, RX, RY, NT, PF) \
+    {NRR_U16, FMA, B, RX, RY, NT, PF, k_match_surf<uint16_t, FMA, B, RX, RY, NT, PF>}
+#define S32F(B, RX, RY, NT, PF) \
+    {NRR_F32, FMA, B, RX, RY, NT, PF, k_match_surf<float, FMA, B, RX, RY, NT, PF>}
+const Variant kSurfVariants[] = {
+    S16D(3, 4, 4, 256, 0), S16D(5, 4, 4, 256, 0), S16D(7, 3, 7, 256, 1), S16D(9, 5, 5, 256, 0),
+    S16D(11, 3, 3, 256, 0), S16D(13, 3, 3, 256, 0), S16D(15, 2, 2, 256, 0),
+    S16F(7, 4, 4, 256, 0),  S32F(3, 4, 4, 256, 0),  S32F(5, 4, 4, 256, 0),
+    S32F(7, 4, 4, 256, 0),  S32F(9, 5, 5, 256, 0),
+};
+#undef S16D
+#undef S16F
+#undef S32F
+}  // namespace
+
+hipError_t launch_match_surface(nrr_dtype dtype, int32_t arith, const MatchArgs &a,
+                                float *surface, hipStream_t stream) {
+    if (arith == kArithMfma) {
+        if (!mfma_supported(dtype, a.block, a.window) || !mfma_fits(a))
+            return hipErrorNotSupported;
+        return launch_match_mfma(a, stream, surface);
+    }
+    const size_t limit = device_lds_limit();
+    for (const Variant &v : kSurfVariants) {
+        if (v.dtype != dtype || v.arith != arith || v.b != a.block) continue;
+        Plan pl;
+        if (!plan_variant(v, a.window, limit, limit / 2, &pl)) continue;
+        if (hipFuncSetAttribute(reinterpret_cast<const void *>(v.fn),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)pl.lds) != hipSuccess)
+            return hipGetLastError();
+        Params p;
+        p.ref = a.ref;
+        p.flt = a.flt;
+        p.nx = a.nx;
+        p.ny = a.ny;
+        p.nz = a.nz;
+        p.centers = a.centers;
+        p.n = a.n;
+        p.w = a.window;
+        p.cz = pl.cz;
+        p.stats = a.stats;
+        p.pv = a.pairs;
+        p.ox = a.ox;
+        p.oy = a.oy;
+        p.disp = a.disp;
+        p.ncc = a.ncc;
+        p.conf = a.conf;
+        p.surface = surface;
+        const int64_t chunk = 1ll << 30;
+        for (int64_t first = 0; first < a.n; first += chunk) {
+            p.first = first;
+            const int64_t cnt = a.n - first < chunk ? a.n - first : chunk;
+            hipLaunchKernelGGL(v.fn, dim3((unsigned)cnt), dim3(v.nt), pl.lds, stream, p);
+        }
+        return hipGetLastError();
+    }
+    return hipErrorNotSupported;
 }
 
 }  // namespace nrr

@@ -16,13 +16,18 @@
 // 4-column by 2-row groups of (x', y') that any column of the patch touches.
 //
 // Exactness and precision: 12-bit voxels centred on an integer c are exact in
-// fp16 when |v - c| <= 2048; c starts at the block's rounded mean and is
-// clamped into [max - 2048, min + 2048] over the block and its window, which
-// is never empty for 12-bit data, so every product is exact and only the
-// FP32 accumulation rounds.  The centred operands keep the partial sums near
-// the match small (relative rounding ~1e-7), the ranking key follows the
-// exact integer window statistics, and the winner's NCC is recomputed in
-// exact integer arithmetic from the staged operands.
+// fp16 when |v - c| <= 2048.  The block and its window take a constant each,
+// both starting at the block's rounded mean: c_T clamped into [max - 2048,
+// min + 2048] over the block, c_F into the same interval over the window
+// (neither is ever empty for 12-bit data), so every product is exact and only
+// the FP32 accumulation rounds.  T - c_T sums to at most about N/2 in
+// magnitude, so the terms that cancel in N X - S_T S_F stay small even where
+// the window holds values far from the block's (a single constant clamped
+// over both would leave T - c far from zero mean there, and FP32 partial sums
+// N times the covariance's size); F - c_F is centred for the displacements
+// that look like the block, where the ranking has to be accurate.  The
+// ranking key follows the exact integer window statistics, and the winner's
+// NCC is recomputed in exact integer arithmetic from the staged operands.
 //
 // Data flow of one workgroup (one selected block):
 //  * the block's clipped window is staged in LDS as fp16 (v - c), rows padded
@@ -94,6 +99,9 @@ struct MfParams {
     int32_t *disp;
     float *ncc;
     float *conf;
+    // optional [n][2w+1]^3 ranking NCC of every valid displacement (the
+    // diagnostic instantiation only)
+    float *surface;
 };
 
 __device__ inline int64_t xcd_order(int64_t wg, int64_t n) {
@@ -118,7 +126,7 @@ __device__ inline void put(const MfParams &p, int64_t blk, int dx, int dy, int d
 constexpr int MAX_NW = 4;  // wavefronts per workgroup
 struct MfSmall {
     long long red[MAX_NW * 4];
-    int mm[MAX_NW * 2];
+    int mm[MAX_NW * 4];
     float key[MAX_NW];
     int idx[MAX_NW];
 };
@@ -296,21 +304,21 @@ __device__ __attribute__((always_inline)) inline void build_bop(
 // This wavefront's tiles of the block's search over the centred window
 // `win` (row pitch rp, plane pitch pl halves): keeps the lane's best (key,
 // shift index).  key = (N C - S_T S_F) * rsqrt(N varF), with S_T = sum (T -
-// c) and S_F = sum (F - c) = s + N (2048 - c) (the table's s sums F - 2048):
-// S_T S_F = S_T s + S_T N (2048 - c), both terms in FP32 from exact integers
-// (relative error 2^-24 of terms that are at most N^2 2048^2).
-template <int B, int NW>
+// c_T) and S_F = sum (F - c_F) = s + N (2048 - c_F) (the table's s sums
+// F - 2048): S_T S_F = S_T s + S_T N (2048 - c_F), both terms in FP32 from
+// exact integers (relative error 2^-24 of terms at most |S_T| N 2048).
+template <int B, int NW, bool SURF>
 __device__ __attribute__((always_inline)) inline void sweep_tiles(
-    const MfParams &p, const BGeo &g, const _Float16 *win, int rp, int pl,
-    const half8 (&bop)[B][KGeo<B>::NQ], long long sTc, int c, int wave, int lane, float &bk,
-    int &bi) {
+    const MfParams &p, const BGeo &g, int64_t blk, const _Float16 *win, int rp, int pl,
+    const half8 (&bop)[B][KGeo<B>::NQ], long long sTc, float inv_vt, int cf, int wave, int lane,
+    float &bk, int &bi) {
     using G = KGeo<B>;
     constexpr int N = B * B * B, NQ = G::NQ;
     const Tiling &tl = g.tl;
     const int n16 = lane & 15, grp = lane >> 4;
     const int oa = n16 & 3, ob = n16 >> 2;
     const float fN = (float)N, fST = (float)sTc;
-    const float fshift = (float)(sTc * (long long)N * (2048 - c));
+    const float fshift = (float)(sTc * (long long)N * (2048 - cf));
     const int side = 2 * p.w + 1, side2 = side * side;
     const int plane_rec = p.oy * p.ox;
     for (int tile = wave; tile < tl.ntiles; tile += NW) {
@@ -380,6 +388,8 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
                 const float key = valid ? cov * rec0[i].r : -INFINITY;
                 const int idx = valid ? (g.loz + dz + p.w) * side2 + oxy[i] : INT_MAX;
                 keep_best(bk, bi, key, idx);
+                if constexpr (SURF)  // NCC = key / sqrt(N varT)
+                    if (valid) p.surface[blk * side2 * side + idx] = key * inv_vt;
             }
             fetch(tau + 1, rec0);
         };
@@ -393,13 +403,14 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
 }
 
 // Workgroup argmax of the lanes' (key, index), then the exact NCC at the
-// winner from the staged integers (v - c), written by thread 0.  Every
+// winner from the staged integers (F - c_F in the window, T - c_T in the
+// table; the NCC does not depend on either constant), written by thread 0.  Every
 // thread of the workgroup calls it; it ends with a barrier.
 template <int B, int NW>
 __device__ __attribute__((always_inline)) inline void finish_block(
     const MfParams &p, const BGeo &g, int64_t blk, const _Float16 *win, int rp, int pl,
     const _Float16 *tt, long long st, long long stt, int c, float bk, int bi, MfSmall &sm,
-    int tid) {
+    int tid) {  // c: the block's constant c_T
     using G = KGeo<B>;
     constexpr int N = B * B * B, NT = 64 * NW;
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -464,40 +475,47 @@ __device__ __attribute__((always_inline)) inline void finish_block(
     __syncthreads();
 }
 
-// Workgroup reduction of the block sums and the value range; every thread
-// returns the totals.
+// Workgroup reduction of the block sums and the value ranges (block: tmin,
+// tmax; window: vmin, vmax); every thread returns the totals.
 template <int NW>
-__device__ inline void reduce_block(long long &st, long long &stt, int &vmin, int &vmax,
-                                    MfSmall &sm, int tid) {
+__device__ inline void reduce_block(long long &st, long long &stt, int &tmin, int &tmax,
+                                    int &vmin, int &vmax, MfSmall &sm, int tid) {
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     for (int off = 32; off > 0; off >>= 1) {
         st += __shfl_xor(st, off);
         stt += __shfl_xor(stt, off);
+        tmin = min(tmin, __shfl_xor(tmin, off));
+        tmax = max(tmax, __shfl_xor(tmax, off));
         vmin = min(vmin, __shfl_xor(vmin, off));
         vmax = max(vmax, __shfl_xor(vmax, off));
     }
     if (lane == 0) {
         sm.red[wave * 4] = st;
         sm.red[wave * 4 + 1] = stt;
-        sm.mm[wave * 2] = vmin;
-        sm.mm[wave * 2 + 1] = vmax;
+        sm.mm[wave * 4] = tmin;
+        sm.mm[wave * 4 + 1] = tmax;
+        sm.mm[wave * 4 + 2] = vmin;
+        sm.mm[wave * 4 + 3] = vmax;
     }
     __syncthreads();
     st = 0;
     stt = 0;
-    vmin = 4095;
-    vmax = 0;
+    tmin = vmin = 4095;
+    tmax = vmax = 0;
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
         st += sm.red[i * 4];
         stt += sm.red[i * 4 + 1];
-        vmin = min(vmin, sm.mm[i * 2]);
-        vmax = max(vmax, sm.mm[i * 2 + 1]);
+        tmin = min(tmin, sm.mm[i * 4]);
+        tmax = max(tmax, sm.mm[i * 4 + 1]);
+        vmin = min(vmin, sm.mm[i * 4 + 2]);
+        vmax = max(vmax, sm.mm[i * 4 + 3]);
     }
 }
 
-// The centre: the block's rounded mean, clamped so every |v - c| <= 2048
-// over the staged voxels (12-bit values, so the interval is never empty).
+// A centre: the block's rounded mean, clamped so every |v - c| <= 2048 over
+// the values of range [vmin, vmax] (12-bit values: the interval is never
+// empty).
 __device__ inline int centre(long long st, int n, int vmin, int vmax) {
     return min(max((int)llrint((double)st / (double)n), vmax - 2048), vmin + 2048);
 }
@@ -519,7 +537,7 @@ __device__ inline u32x4 centre_chunk(u32x4 v, i16x2 c2) {
 // register file of one.
 constexpr int PB_NW = 4;
 
-template <int B>
+template <int B, bool SURF>
 __global__ __launch_bounds__(64 * PB_NW, B <= 7 ? 2 : 1) void k_match_mfma(MfParams p) {
     using G = KGeo<B>;
     constexpr int H = (B - 1) / 2, N = B * B * B, NQ = G::NQ, NT = 64 * PB_NW;
@@ -550,8 +568,8 @@ __global__ __launch_bounds__(64 * PB_NW, B <= 7 ? 2 : 1) void k_match_mfma(MfPar
         const int oz = o / (B * B), oy = (o / B) % B, ox = o % B;
         tv[k] = p.ref[((int64_t)(g.cz - H + oz) * p.ny + (g.cy - H + oy)) * p.nx + (g.cx - H + ox)];
     }
-    // The range that clamps the centre covers every staged voxel: the window
-    // and the few neighbouring voxels its padded rows pick up.
+    // The range that clamps the window's centre covers every staged voxel: the
+    // window and the few neighbouring voxels its padded rows pick up.
     u16x2 mn2 = {4095, 4095}, mx2 = {0, 0};
     {
         // chunk coordinates advance by NT chunks per step (no divisions)
@@ -598,26 +616,29 @@ __global__ __launch_bounds__(64 * PB_NW, B <= 7 ? 2 : 1) void k_match_mfma(MfPar
         }
     }
     int vmin = min((int)mn2[0], (int)mn2[1]), vmax = max((int)mx2[0], (int)mx2[1]);
+    int tmin = 4095, tmax = 0;
     long long st = 0, stt = 0;
 #pragma unroll
     for (int k = 0; k < TPT; ++k) {
         if (tid + k * NT >= N) continue;
         st += tv[k];
         stt += (long long)tv[k] * tv[k];
-        vmin = min(vmin, tv[k]);
-        vmax = max(vmax, tv[k]);
+        tmin = min(tmin, tv[k]);
+        tmax = max(tmax, tv[k]);
     }
-    reduce_block<PB_NW>(st, stt, vmin, vmax, sm, tid);
+    reduce_block<PB_NW>(st, stt, tmin, tmax, vmin, vmax, sm, tid);
     if ((long long)N * stt - st * st == 0) {  // flat block: every NCC is 0
         if (tid == 0) put(p, blk, g.lox, g.loy, g.loz, 0.0f);
         return;
     }
-    const int c = centre(st, N, vmin, vmax);
+    const int c = centre(st, N, tmin, tmax);    // c_T
+    const int cf = centre(st, N, vmin, vmax);  // c_F
 
     // ---- pass 2: centre the staged planes in place (whole planes, padding
-    // included: those halves are never read) and the bordered table of T - c
+    // included: those halves are never read) on c_F, and the bordered table
+    // of T - c_T
     {
-        const i16x2 c2 = {(short)c, (short)c};
+        const i16x2 c2 = {(short)cf, (short)cf};
         const int nq = g.ez * pl / 8;  // pl is a multiple of 8 halves
         for (int i = tid; i < nq; i += NT) {
             u32x4 *a = reinterpret_cast<u32x4 *>(win + 8 * i);
@@ -637,7 +658,13 @@ __global__ __launch_bounds__(64 * PB_NW, B <= 7 ? 2 : 1) void k_match_mfma(MfPar
     build_bop<B>(tt, lane, bop);
     float bk = -INFINITY;
     int bi = INT_MAX;
-    sweep_tiles<B, PB_NW>(p, g, win, rp, pl, bop, st - (long long)N * c, c, wave, lane, bk, bi);
+    const long long sTc = st - (long long)N * c;
+    float inv_vt = 0.0f;
+    if constexpr (SURF) {  // 1 / sqrt(N sum (T - c)^2 - (sum (T - c))^2), exact integers
+        const long long tc2 = stt - 2ll * c * st + (long long)N * c * c;
+        inv_vt = (float)(1.0 / sqrt((double)((long long)N * tc2 - sTc * sTc)));
+    }
+    sweep_tiles<B, PB_NW, SURF>(p, g, blk, win, rp, pl, bop, sTc, inv_vt, cf, wave, lane, bk, bi);
     finish_block<B, PB_NW>(p, g, blk, win, rp, pl, tt, st, stt, c, bk, bi, sm, tid);
 }
 
@@ -646,11 +673,11 @@ typedef void (*mf_kernel_t)(MfParams);
 
 struct MfVariant {
     int b;
-    mf_kernel_t fn;
+    mf_kernel_t fn, surf;
     int tt_bytes;
 };
 
-#define MFV(B) {B, k_match_mfma<B>, KGeo<B>::TT_BYTES}
+#define MFV(B) {B, k_match_mfma<B, false>, k_match_mfma<B, true>, KGeo<B>::TT_BYTES}
 const MfVariant kMfVariants[] = {MFV(3), MFV(5), MFV(7), MFV(9)};
 #undef MFV
 
@@ -700,7 +727,7 @@ bool mfma_fits(const MatchArgs &a) {
     return (int64_t)a.ox * a.oy * (a.nz - a.block + 1) < (1ll << 31);
 }
 
-hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream) {
+hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream, float *surface) {
     MfPlan pl;
     if (!mf_plan(a.block, a.window, device_lds_limit(), &pl) || !mfma_fits(a))
         return hipErrorInvalidValue;
@@ -722,14 +749,16 @@ hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream) {
     p.disp = a.disp;
     p.ncc = a.ncc;
     p.conf = a.conf;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(v->fn),
+    p.surface = surface;
+    const mf_kernel_t fn = surface ? v->surf : v->fn;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds);
     if (e != hipSuccess) return e;
     const int64_t chunk = 1ll << 30;
     for (int64_t first = 0; first < a.n; first += chunk) {
         p.first = first;
         const int64_t cnt = a.n - first < chunk ? a.n - first : chunk;
-        hipLaunchKernelGGL(v->fn, dim3((unsigned)cnt), dim3(64 * PB_NW), pl.lds, stream, p);
+        hipLaunchKernelGGL(fn, dim3((unsigned)cnt), dim3(64 * PB_NW), pl.lds, stream, p);
     }
     return hipGetLastError();
 }

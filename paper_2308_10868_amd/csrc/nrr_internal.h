@@ -167,6 +167,13 @@ hipError_t launch_match_batch(nrr_dtype dtype, const BatchSet *sets, int32_t nse
 struct TileShape {
     int32_t arith, rx, ry, nt, pf, cz;
 };
+// The search in form `arith` (0 dot2, 1 FMA, 2 MFMA) also writing the
+// ranking NCC of every valid displacement to surface[n][2w+1]^3 (a
+// diagnostic; hipErrorNotSupported when no such instantiation serves).
+hipError_t launch_match_surface(nrr_dtype dtype, int32_t arith, const MatchArgs &a,
+                                float *surface, hipStream_t stream);
+// p[0..n) = v on the stream (a kernel, no memset).
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t stream);
 // The shape launch_match would use now (arith 0 dot2, 1 FMA, 2 MFMA); false
 // when no compiled shape serves.
 bool match_plan(nrr_dtype dtype, const MatchArgs &a, TileShape *out);
@@ -189,7 +196,9 @@ void clear_tuned_shapes();
 // window in LDS): whether it serves (dtype, block, window), and its launch.
 bool mfma_supported(nrr_dtype dtype, int32_t block, int32_t window);
 bool mfma_fits(const MatchArgs &a);  // volume small enough for its 32-bit indices
-hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream);
+// surface (optional): [n][2w+1]^3 ranking NCC of every valid displacement
+// (a diagnostic instantiation; entries of invalid displacements untouched).
+hipError_t launch_match_mfma(const MatchArgs &a, hipStream_t stream, float *surface = nullptr);
 constexpr int32_t kArithMfma = 2;  // TileShape::arith of the matrix-core form
 
 // LDS bytes per workgroup available on the current device (cached).
