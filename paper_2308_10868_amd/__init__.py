@@ -93,7 +93,9 @@ class _ServerInfo(ctypes.Structure):
                 ("used_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
                 ("max_running", ctypes.c_int32), ("submitted", ctypes.c_int64),
                 ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
-                ("pending", ctypes.c_int64)]
+                ("pending", ctypes.c_int64), ("wall_ms", ctypes.c_double),
+                ("busy_ms", ctypes.c_double), ("volumes", ctypes.c_int64),
+                ("records", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -162,6 +164,10 @@ def load():
         "nrr_request_footprint": (st, [P, P]),
         "nrr_server_create": (st, [SZ, I32, P]),
         "nrr_server_submit": (st, [P, P, P]),
+        "nrr_server_submit_resident": (st, [P, P, I64, I64, P]),
+        "nrr_server_add_volume": (st, [P, P, I32, P, P]),
+        "nrr_server_remove_volume": (st, [P, I64]),
+        "nrr_server_release": (st, [P, I64]),
         "nrr_server_poll": (st, [P, I64, P]),
         "nrr_server_wait": (st, [P, I64, P]),
         "nrr_server_stats": (st, [P, P]),
@@ -646,13 +652,34 @@ def _host_or_dev_info(t):
     return dt, (nx, ny, nz)
 
 
+class Volume:
+    """A volume held in a server's memory (Server.add_volume); requests name
+    it in place of a tensor."""
+
+    def __init__(self, server, vid, dtype, dims):
+        self.server, self.id, self.dtype, self.dims = server, vid, dtype, dims
+
+    def remove(self):
+        """Free the volume (all requests naming it must have finished)."""
+        if self.id and getattr(self.server, "_h", None) is not None:
+            _check(load().nrr_server_remove_volume(self.server._h, self.id))
+        self.id = 0
+
+
+def _vol_or_tensor(v):
+    if isinstance(v, Volume):
+        return v.dtype, v.dims, None, v.id
+    dt, dims = _host_or_dev_info(v)
+    return dt, dims, v.data_ptr(), 0
+
+
 def _make_request(ref, flt, block, stride, window, fraction, outs=None):
-    dt, dims = _host_or_dev_info(ref)
-    dt2, dims2 = _host_or_dev_info(flt)
+    dt, dims, rp, _ = _vol_or_tensor(ref)
+    dt2, dims2, fp, _ = _vol_or_tensor(flt)
     if dt != dt2 or dims != dims2:
         raise NrrError(1, "ref and flt must share dtype and shape")
     r = _Request()
-    r.ref, r.flt, r.dtype = ref.data_ptr(), flt.data_ptr(), dt
+    r.ref, r.flt, r.dtype = rp, fp, dt
     r.dims[:] = list(dims)
     r.block, r.stride, r.window, r.fraction = int(block), int(stride), int(window), float(fraction)
     if outs is not None:
@@ -677,20 +704,30 @@ class Job:
 
     def __init__(self, server, ticket, keep, outs, k):
         self.server, self.ticket, self._keep = server, ticket, keep
+        self._info = None
         self.centers, self.disp, self.ncc, self.conf = [o[:k] for o in outs]
         self.k = k
 
     def poll(self):
+        if self._info is not None:
+            return dict(self._info)
         info = _RequestInfo()
         _check(load().nrr_server_poll(self.server._h, self.ticket, ctypes.byref(info)))
         return info.as_dict()
 
     def wait(self):
+        """Block until the request finishes; its record is then released in
+        the server (later poll()/wait() return the same information)."""
+        if self._info is not None:
+            return dict(self._info)
         info = _RequestInfo()
         st = load().nrr_server_wait(self.server._h, self.ticket, ctypes.byref(info))
+        if st in (0, 3):  # finished (done, or failed on the device)
+            _check(load().nrr_server_release(self.server._h, self.ticket))
+            self._keep = None
+            self._info = info.as_dict()
         _check(st)
-        self._keep = None
-        return info.as_dict()
+        return dict(self._info)
 
 
 class Server:
@@ -702,14 +739,28 @@ class Server:
         _check(load().nrr_server_create(int(device_bytes), int(slots), ctypes.byref(h)))
         self._h = h
 
+    def add_volume(self, vol) -> Volume:
+        """Copy a [nz, ny, nx] host or device tensor into the server's memory
+        once; requests may then name the returned Volume in place of it."""
+        torch = _torch()
+        dt, dims = _host_or_dev_info(vol)
+        if vol.is_cuda:
+            torch.cuda.current_stream(vol.device).synchronize()  # the copy is ordered after nothing
+        vid = ctypes.c_int64()
+        _check(load().nrr_server_add_volume(self._h, ctypes.c_void_p(vol.data_ptr()), dt,
+                                            _dims3(dims), ctypes.byref(vid)))
+        return Volume(self, vid.value, dt, dims)
+
     def submit(self, ref, flt, block: int, stride: int, window: int, fraction: float,
                out=None) -> Job:
         """Queue one registration.  `ref`/`flt` are [nz, ny, nx] host (ideally
-        page-locked) or device tensors, kept alive until the job completes.
-        Results go to `out` = (centers, disp, ncc, conf) tensors of >= K rows
-        if given, else to new page-locked host tensors."""
+        page-locked) or device tensors, kept alive until the job completes,
+        or Volumes added to this server.  Results go to `out` = (centers,
+        disp, ncc, conf) tensors of >= K rows if given, else to new
+        page-locked host tensors."""
         torch = _torch()
-        dt, dims = _host_or_dev_info(ref)
+        dt, dims, _, ref_id = _vol_or_tensor(ref)
+        flt_id = _vol_or_tensor(flt)[3]
         k = select_count(dims, block, stride, fraction)
         if out is None:
             rows = max(k, 1)
@@ -719,7 +770,8 @@ class Server:
                    torch.empty(rows, dtype=torch.float32, pin_memory=True))
         r, _, _ = _make_request(ref, flt, block, stride, window, fraction, out)
         t = ctypes.c_int64()
-        _check(load().nrr_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        _check(load().nrr_server_submit_resident(self._h, ctypes.byref(r), ref_id, flt_id,
+                                                 ctypes.byref(t)))
         return Job(self, t.value, (ref, flt), out, k)
 
     def stats(self):

@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 import paper_2308_10868_amd as nrr
 from paper_2308_10868_amd import synth
 from tests.gpu_util import check_match, to_dev, to_host
@@ -93,8 +94,115 @@ def test_served_equals_plain_calls_and_oracle(torch_dev, mix):
         torch.cuda.synchronize()
         assert np.array_equal(c, to_host(cp))
         assert np.array_equal(d, to_host(dp)) and np.array_equal(n, to_host(np_))
-    q, (c, d, n, f) = mix[0], out[0]
-    check_match(q["pair"].ref, q["pair"].flt, c, q["block"], q["window"], d, n, f, "served")
+
+
+
+def test_every_served_request_meets_the_oracle(torch_dev, mix):
+    say("serving: all 8 requests of the mix vs oracle")
+    out, _, _ = serve(mix, slots=4, device_bytes=1 << 30)
+    for i, (q, (c, d, n, f)) in enumerate(zip(mix, out)):
+        c_o, _ = oracle.select(q["pair"].ref, q["block"], q["stride"], q["fraction"])
+        assert np.array_equal(c, c_o), i
+        check_match(q["pair"].ref, q["pair"].flt, c, q["block"], q["window"], d, n, f,
+                    "served %d" % i)
+
+
+@pytest.mark.parametrize("size,block", [((192, 192, 96), 7), ((384, 384, 160), 9)])
+def test_large_served_requests_with_window_15(torch_dev, size, block):
+    """Clinical-size requests with the largest served window, beside a small
+    one, against the oracle on 160 seeded blocks (a quarter near a face)."""
+    torch = torch_dev
+    w = 15
+    p = synth.gen_blobs_u16(seed=1000, dims=size, peak=(4.0, 10.0))
+    small = synth.gen_mri_u16(seed=30, dims=(64, 64, 64))
+    say("serving: %s b%d W%d" % (size, block, w))
+    srv = nrr.Server(device_bytes=4 << 30, slots=2)
+    big = srv.submit(pinned(p.ref, torch), pinned(p.flt, torch), block, block, w, 0.2)
+    other = srv.submit(pinned(small.ref, torch), pinned(small.flt, torch), 5, 5, 6, 0.2)
+    big.wait()
+    other.wait()
+    srv.close()
+    c, d, n, f = (to_host(t) for t in (big.centers, big.disp, big.ncc, big.conf))
+    c_o, _ = oracle.select(p.ref, block, block, 0.2)
+    assert np.array_equal(c, c_o)
+    h = block // 2
+    dims = np.array(size)
+    near = np.flatnonzero(np.any((c - h - w < 0) | (c + h + w > dims - 1), axis=1))
+    far = np.setdiff1d(np.arange(len(c)), near)
+    rng = np.random.default_rng(5)
+    idx = np.sort(np.concatenate([rng.choice(near, min(40, len(near)), replace=False),
+                                  rng.choice(far, 120, replace=False)]))
+    check_match(p.ref, p.flt, c[idx], block, w, d[idx], n[idx], f[idx],
+                "served %s b%d W%d" % (size, block, w))
+
+
+def test_resident_volumes_and_cached_selection(torch_dev, mix):
+    """Requests naming resident volumes give the uploaded requests' results;
+    a resident ref's selection is computed once per parameter set and then
+    shared; finished records are released; a volume in use cannot go."""
+    torch = torch_dev
+    say("serving: resident volumes")
+    q0, q1 = mix[0], mix[1]
+    base, _, _ = serve([q0, q1, q0, q1], slots=1, device_bytes=1 << 30, one_at_a_time=True)
+    srv = nrr.Server(device_bytes=1 << 30, slots=3)
+    vols = {}
+    for i, q in enumerate((q0, q1)):
+        dev_ref = to_dev(q["pair"].ref)  # one from device memory, one from host memory
+        vols[i] = (srv.add_volume(dev_ref if i == 0 else q["ref"]), srv.add_volume(q["flt"]))
+    assert srv.stats()["volumes"] == 4
+    jobs = []
+    for rep in range(3):  # the same parameters again: the kept selection serves them
+        for i, q in enumerate((q0, q1)):
+            jobs.append((i, srv.submit(vols[i][0], vols[i][1], q["block"], q["stride"],
+                                       q["window"], q["fraction"])))
+    # a resident ref with an uploaded flt
+    jobs.append((0, srv.submit(vols[0][0], q0["flt"], q0["block"], q0["stride"], q0["window"],
+                               q0["fraction"])))
+    for i, j in jobs:
+        info = j.wait()
+        assert info["state"] == 2
+        got = tuple(to_host(t) for t in (j.centers, j.disp, j.ncc, j.conf))
+        for x, y in zip(base[i], got):
+            assert np.array_equal(x, y, equal_nan=True), i
+    st = srv.stats()
+    assert st["records"] == 0, st  # every waited request was released
+    assert 0.0 < st["busy_ms"] <= st["wall_ms"], st
+    # the library checks a named volume against the request's dtype and dims
+    import ctypes
+
+    outs = (torch.empty((4096, 3), dtype=torch.int32), torch.empty((4096, 3), dtype=torch.int32),
+            torch.empty(4096), torch.empty(4096))
+    r, _, _ = nrr._make_request(q1["ref"], q1["flt"], 5, 5, 3, 0.1, outs)
+    t = ctypes.c_int64()
+    assert nrr.load().nrr_server_submit_resident(srv._h, ctypes.byref(r), vols[0][0].id, 0,
+                                                 ctypes.byref(t)) == 1
+    assert nrr.load().nrr_server_submit_resident(srv._h, ctypes.byref(r), 0, 999,
+                                                 ctypes.byref(t)) == 1
+    for r, f in vols.values():
+        r.remove()
+        f.remove()
+    assert srv.stats()["volumes"] == 0
+    assert srv.stats()["used_bytes"] == 0
+    srv.close()
+
+
+def test_volume_in_use_cannot_be_removed(torch_dev, mix):
+    torch = torch_dev
+    say("serving: removing a volume in use")
+    big = synth.gen_blobs_u16(seed=1001, dims=(192, 192, 96), peak=(4.0, 10.0))
+    q = mix[0]
+    srv = nrr.Server(device_bytes=1 << 30, slots=1)
+    vol = srv.add_volume(q["ref"])
+    # one slot: the request naming the volume queues behind a long one
+    blocker = srv.submit(pinned(big.ref, torch), pinned(big.flt, torch), 7, 7, 15, 0.3)
+    j = srv.submit(vol, q["flt"], q["block"], q["stride"], q["window"], q["fraction"])
+    with pytest.raises(nrr.NrrError):
+        vol.remove()
+    blocker.wait()
+    j.wait()
+    vol.remove()
+    assert srv.stats()["used_bytes"] == 0
+    srv.close()
 
 
 def test_admission_respects_device_memory(torch_dev, mix):
