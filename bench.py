@@ -40,7 +40,10 @@ BATCHED = "batched_64_f32_32sets"
 # the registration server: Poisson arrivals of mixed-size requests
 SERVING = "serving_poisson_4hz"
 # selection inside a region mask with a connectivity pattern, on the MRI pair
+# (one-workgroup path) and on the dense 512x512x256 grid (round launches)
 SELECT_EX = "mri_select_ex_u16"
+SELECT_EX_DENSE = "blobs_select_ex_u16"
+SELECT_EX_CFG = {SELECT_EX: ("mri", 7, 7, 0.25, 6), SELECT_EX_DENSE: ("blobs", 9, 5, 0.70, 6)}
 # per-axis sizes on the MRI pair: blocks thinner along z (slice axis)
 ANISO = "mri_aniso_256x256x124_u16"
 ANISO_CFG = {"block": (7, 7, 3), "stride": (7, 7, 3), "fraction": 0.25, "window": (10, 10, 4)}
@@ -172,7 +175,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="mri_256x256x124_u16",
-                    choices=sorted(WORKLOADS) + [BATCHED, SERVING, ANISO, SELECT_EX])
+                    choices=sorted(WORKLOADS) + [BATCHED, SERVING, ANISO, SELECT_EX,
+                                                 SELECT_EX_DENSE])
     ap.add_argument("--requests", type=int, default=48,
                     help="requests of the serving workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -211,7 +215,7 @@ def main() -> int:
         return bench_serving(args)
     if args.workload == ANISO:
         return bench_aniso(args)
-    if args.workload == SELECT_EX:
+    if args.workload in SELECT_EX_CFG:
         return bench_select_ex(args)
 
     import torch
@@ -576,19 +580,22 @@ def ellipsoid_mask(shape_zyx):
 
 
 def bench_select_ex(args) -> int:
-    """The selection variants alone: keys of every candidate block of the MRI
-    pair's ref (7^3, stride 7: 22,032 candidates), candidates restricted to a
-    region mask, 6-connectivity greedy in rank order, K from F = 0.25 of the
-    masked candidates.  Roofline: HBM (one read of ref and of the mask at
-    the candidate centres, keys written and read once)."""
+    """The selection variants alone: keys of every candidate block of the
+    ref, candidates restricted to a region mask, 6-connectivity greedy in
+    rank order, K from F of the masked candidates.  The MRI pair (7^3, stride
+    7: 22,032 candidates, one workgroup) or the dense 512x512x256 volume
+    (9^3, stride 5: 510,050 candidates, round launches; the call waits on the
+    stream between rounds, so the step is timed on the host).  Roofline: HBM
+    (one read of ref and of the mask at the candidate centres, keys written
+    and read once)."""
     import ctypes
 
     import torch
 
     import paper_2308_10868_amd as nrr
 
-    b, st, frac, conn = 7, 7, 0.25, 6
-    pair = make_pair("mri", args.seed)
+    kind, b, st, frac, conn = SELECT_EX_CFG[args.workload]
+    pair = make_pair(kind, args.seed)
     mask_h = ellipsoid_mask(pair.ref.shape)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -627,6 +634,7 @@ def bench_select_ex(args) -> int:
     ms_step = (time.perf_counter() - t) * 1e3 / args.steps
     kern_ms = float(np.mean([a.elapsed_time(e) for a, e in evs]))
     k = int(kd.item())
+    h = b // 2
     grid = [(d - b) // st + 1 for d in dims]
     ncand = grid[0] * grid[1] * grid[2]
     # algorithmic bytes: every candidate block read once from ref (the grid
@@ -646,17 +654,20 @@ def bench_select_ex(args) -> int:
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": SELECT_EX, "dims_xyz": list(dims), "block": b, "stride": st,
+        "config": {"workload": args.workload, "dims_xyz": list(dims), "block": b, "stride": st,
                    "fraction": frac, "connectivity": conn, "candidates": ncand,
-                   "masked_candidates": int(mask_h[(np.arange(grid[2]) * st + 3)[:, None, None],
-                                                   (np.arange(grid[1]) * st + 3)[None, :, None],
-                                                   (np.arange(grid[0]) * st + 3)[None, None, :]]
+                   "masked_candidates": int(mask_h[(np.arange(grid[2]) * st + h)[:, None, None],
+                                                   (np.arange(grid[1]) * st + h)[None, :, None],
+                                                   (np.arange(grid[0]) * st + h)[None, None, :]]
                                             .sum()),
                    "taken": k, "seed": args.seed},
         "selection_ms": kern_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                      "frac": achieved / 8000.0, "traffic": None,
-                     "kernel": "k_block_keys_u16 + k_select_ex (one launch each)"},
+                     "kernel": "k_block_keys_u16 + k_select_ex (one launch each)"
+                     if ncand <= 24576 else
+                     "k_block_keys_u16, k_ex_init, k_ex_round launches, k_ex_count, radix "
+                     "select (the whole selection, host waits between rounds included)"},
     }
     if args.cpu_budget > 0:
         import oracle

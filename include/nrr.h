@@ -83,7 +83,9 @@ nrr_status nrr_grid_shape(const int32_t dims[3], int32_t block, int32_t stride, 
 nrr_status nrr_select_count(const int32_t dims[3], int32_t block, int32_t stride, double fraction,
                             int64_t *k);
 
-/* Device workspace bytes nrr_select_blocks needs for these sizes. */
+/* Device workspace bytes nrr_select_blocks and nrr_select_blocks_ex need
+ * for these sizes (the variants on grids of more than 24576 candidates take
+ * 5 bytes per candidate more than the plain selection). */
 nrr_status nrr_select_workspace_bytes(const int32_t dims[3], int32_t block, int32_t stride,
                                       size_t *bytes);
 
@@ -130,8 +132,8 @@ nrr_status nrr_select_blocks(const void *vol, nrr_dtype dtype, const int32_t dim
  *
  * Calls that overlap on one GPU (concurrent streams, or host threads
  * sharing a device) share that array and race: serialise them.  Errors as
- * nrr_select_blocks, plus UNSUPPORTED when nrr_select_workspace_bytes for
- * these sizes exceeds 32 MiB (about 4.19 million candidate blocks) or the
+ * nrr_select_blocks, plus UNSUPPORTED when the plain selection's workspace
+ * for these sizes exceeds 32 MiB (about 4.19 million candidate blocks) or the
  * device index is 64 or more, HIP if the array's address cannot be found. */
 nrr_status nrr_select_blocks_static(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                     int32_t block, int32_t stride, double fraction,
@@ -155,10 +157,15 @@ nrr_status nrr_select_blocks_static(const void *vol, nrr_dtype dtype, const int3
  *  centers       device int32 [capacity][3]: the taken centres in ascending
  *                grid index; capacity >= floor(0.5 + grid count * fraction)
  *                (the count without a mask).
- *  k_device      device int64: receives the number taken (asynchronously).
+ *  k_device      device int64: receives the number taken.
  *  workspace     device, >= nrr_select_workspace_bytes().
+ * Grids of up to 24576 candidates are selected by one workgroup and the call
+ * returns without waiting.  Larger grids are selected in rounds (each settles
+ * at least the best candidate still open) and the call waits on `stream`
+ * after each round to see whether another is needed, so it returns when the
+ * stream has reached the final selection kernels (not capturable in a graph).
  * Errors: INVALID_ARG (as nrr_select_blocks; connectivity not 0/6/18/26),
- * BUFFER_TOO_SMALL, UNSUPPORTED (more than 24576 candidates), HIP. */
+ * BUFFER_TOO_SMALL, UNSUPPORTED (2^31 candidates or more), HIP. */
 nrr_status nrr_select_blocks_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                 int32_t block, int32_t stride, double fraction,
                                 const uint8_t *mask, int32_t connectivity, int32_t *centers,

@@ -122,7 +122,7 @@ nrr_status nrr_select_workspace_bytes(const int32_t dims[3], int32_t block, int3
     int32_t g[3];
     nrr_status s = check_grid(dims, block, stride, g);
     if (s != NRR_OK) return s;
-    *bytes = nrr::select_layout((int64_t)g[0] * g[1] * g[2]).total;
+    *bytes = nrr::select_layout((int64_t)g[0] * g[1] * g[2], true).total;
     return ok();
 }
 
@@ -221,14 +221,13 @@ nrr_status nrr_select_blocks_ex(const void *vol, nrr_dtype dtype, const int32_t 
     if (!vol || !centers || !k_device || !workspace)
         return fail(NRR_ERR_INVALID_ARG, "vol, centers, k_device and workspace must be non-NULL");
     const int64_t n = (int64_t)g[0] * g[1] * g[2];
-    if (n > nrr::kSelectExCand)
-        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (limit %lld for the selection variants)",
-                    (long long)n, (long long)nrr::kSelectExCand);
+    if (n >= (1ll << 31))
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (limit 2^31)", (long long)n);
     const int64_t kmax = count_rule(n, fraction);
     if (capacity < kmax)
         return fail(NRR_ERR_BUFFER_TOO_SMALL, "capacity %lld < %lld", (long long)capacity,
                     (long long)kmax);
-    const nrr::SelectLayout L = nrr::select_layout(n);
+    const nrr::SelectLayout L = nrr::select_layout(n, true);
     if (workspace_bytes < L.total)
         return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
                     L.total);

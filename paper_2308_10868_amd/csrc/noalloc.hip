@@ -29,9 +29,11 @@ nrr_status nrr_select_blocks_static(const void *vol, nrr_dtype dtype, const int3
                                     int32_t block, int32_t stride, double fraction,
                                     int32_t *centers, int64_t capacity, int64_t *k_out,
                                     void *stream) {
-    size_t need = 0;
-    nrr_status s = nrr_select_workspace_bytes(dims, block, stride, &need);
+    int32_t g[3];
+    nrr_status s = nrr_grid_shape(dims, block, stride, g);
     if (s != NRR_OK) return s;
+    // the plain selection's workspace (the selection variants need more)
+    const size_t need = nrr::select_layout((int64_t)g[0] * g[1] * g[2]).total;
     if (need > kScratchBytes)
         return nrr::set_error(NRR_ERR_UNSUPPORTED,
                               "selection needs %zu bytes of scratch; the allocation-free "

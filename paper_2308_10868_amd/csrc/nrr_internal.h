@@ -21,9 +21,11 @@ constexpr int kSelectTile = 2048;  // candidates per compaction workgroup
 
 struct SelectLayout {
     size_t keys_off, state_off, tiles_off, total;
+    size_t ex_ctr_off, ex_state_off, ex_above_off;  // selection variants, large grids
     int64_t n_tiles;
 };
-SelectLayout select_layout(int64_t n_candidates);
+// variants: room for the selection variants on large grids as well
+SelectLayout select_layout(int64_t n_candidates, bool variants = false);
 
 // Candidate grid: per-axis block edge b, stride s and candidate count g
 // (x, y, z); centre of candidate i on an axis = i * s + (b - 1) / 2.
@@ -42,14 +44,24 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
                          const BoxGrid &G, int64_t k, int32_t *centers, void *workspace,
                          hipStream_t stream);
 
-// Selection with a candidate mask and a connectivity pattern (0, 6, 18, 26)
-// for grids of at most kSelectExCand candidates; the number taken goes to
-// *k_device.  Uses the keys part of the selection workspace.
+// Selection with a candidate mask and a connectivity pattern (0, 6, 18, 26);
+// the number taken goes to *k_device.  Grids of at most kSelectExCand
+// candidates run in one workgroup (asynchronously); larger grids in round
+// launches with a wait on the stream after each.
 constexpr int64_t kSelectExCand = 24576;
 hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                             int32_t block, int32_t stride, const int32_t grid[3], double fraction,
                             const uint8_t *mask, int32_t connectivity, int32_t *centers,
                             int64_t *k_device, void *workspace, hipStream_t stream);
+hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                  const BoxGrid &G, double fraction, const uint8_t *mask,
+                                  int32_t connectivity, int32_t *centers, int64_t *k_device,
+                                  void *workspace, hipStream_t stream);
+// The K best keys' candidates as centres in ascending grid index (K = k, or
+// *kd when kd is given).
+void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t k,
+                      const int64_t *kd, int32_t *centers, const SelectLayout &L, char *ws,
+                      hipStream_t stream);
 
 // Batched selection (one workgroup per parameter set) for candidate grids of
 // at most kBatchCand blocks; `centers` points at the set's K output rows.

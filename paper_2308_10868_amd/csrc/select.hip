@@ -113,8 +113,11 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
 
 // Radix select of the K-th largest key (1 <= K <= n), 8 bits per pass from
 // the most significant byte; one workgroup.
+// K comes from `k`, or from *kd when kd is given (a count made on the device);
+// K = 0 selects nothing.
 __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
                                                            int64_t n, int64_t k,
+                                                           const int64_t *__restrict__ kd,
                                                            SelectState *__restrict__ st) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
     if (tid == 0) {
         s_prefix = 0;
         s_mask = 0;
-        s_need = k;
+        s_need = kd ? *kd : k;
         s_or = 0;
         s_bucket = n;
         s_fill = 0;
@@ -263,8 +266,10 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint64_t *__restrict_
 __global__ __launch_bounds__(256) void k_compact(const uint64_t *__restrict__ keys, int64_t n,
                                                  const SelectState *__restrict__ st,
                                                  const int64_t *__restrict__ tiles, BoxGrid G,
-                                                 int64_t k, int32_t *__restrict__ centers) {
+                                                 int64_t k, const int64_t *__restrict__ kd,
+                                                 int32_t *__restrict__ centers) {
     constexpr int PER = kSelectTile / 256;
+    if (kd) k = *kd;
     __shared__ int64_t s_gt[256], s_eq[256];
     __shared__ int64_t s_base[2];
     const uint64_t kth = st->kth;
@@ -557,6 +562,186 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
     if (tid == 0) *k_out = want;
 }
 
+// ---------------------------------------------- selection variants, large grids
+//
+// The same greedy rank-order set on grids of any size, in rounds.  The state
+// of each candidate (0 open, 1 taken, 2 left out, 3 outside the mask) and
+// the mask of its pattern neighbours ranked above it live in global memory.
+// A round launch gives each workgroup a tile of 8 x 8 x 8 candidates, which
+// it iterates in LDS until nothing in the tile changes, reading the states
+// of neighbours outside the tile from global memory (a state only ever goes
+// from open to final, and a candidate is decided only from final states, so
+// reading a neighbour late just delays a decision).  Each launch settles at
+// least the best candidate still open, whose ranked-above neighbours are all
+// final, so launches repeat until none is open.  The K best taken
+// candidates then come from the multi-workgroup radix select, on keys
+// remapped so that only taken candidates can be chosen (taken: key + 1, any
+// other: 0; the order among taken candidates is unchanged).
+constexpr int EXT = 8;  // tile edge (candidates)
+enum { EX_N_IN = 0, EX_OPEN = 1, EX_TAKEN = 3, EX_WANT = 4 };  // counters (EX_OPEN: 2 slots)
+
+struct ExDirs {
+    int n;
+    int8_t j[26], dx[26], dy[26], dz[26];
+};
+
+ExDirs ex_dirs(int connectivity) {
+    ExDirs d{};
+    const int max_steps =
+        connectivity == 6 ? 1 : (connectivity == 18 ? 2 : (connectivity == 26 ? 3 : 0));
+    for (int j = 0; j < 26; ++j) {
+        const int i = j < 13 ? j : j + 1;
+        const int dx = i % 3 - 1, dy = (i / 3) % 3 - 1, dz = i / 9 - 1;
+        if ((dx != 0) + (dy != 0) + (dz != 0) > max_steps) continue;
+        d.j[d.n] = (int8_t)j;
+        d.dx[d.n] = (int8_t)dx;
+        d.dy[d.n] = (int8_t)dy;
+        d.dz[d.n] = (int8_t)dz;
+        ++d.n;
+    }
+    return d;
+}
+
+__global__ __launch_bounds__(256) void k_ex_zero(int64_t *__restrict__ ctr) {
+    if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
+}
+
+// States, ranked-above masks (bit t: pattern neighbour t), candidates inside
+// the mask counted into ctr[EX_N_IN].
+__global__ __launch_bounds__(256) void k_ex_init(const uint64_t *__restrict__ keys, BoxGrid G,
+                                                 int nx, int ny, const uint8_t *__restrict__ mask,
+                                                 ExDirs D, uint8_t *__restrict__ state,
+                                                 uint32_t *__restrict__ above,
+                                                 int64_t *__restrict__ ctr) {
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool in = false;
+    if (g < n) {
+        const int64_t gxy = (int64_t)G.g[0] * G.g[1];
+        const int iz = (int)(g / gxy), r = (int)(g - iz * gxy), iy = r / G.g[0],
+                  ix = r - iy * G.g[0];
+        in = true;
+        if (mask)
+            in = mask[((int64_t)(iz * G.s[2] + (G.b[2] - 1) / 2) * ny +
+                       (iy * G.s[1] + (G.b[1] - 1) / 2)) * nx +
+                      (ix * G.s[0] + (G.b[0] - 1) / 2)] != 0;
+        uint32_t bits = 0;
+        const uint64_t kg = keys[g];
+        for (int t = 0; t < D.n; ++t) {
+            const int x = ix + D.dx[t], y = iy + D.dy[t], z = iz + D.dz[t];
+            if (x < 0 || y < 0 || z < 0 || x >= G.g[0] || y >= G.g[1] || z >= G.g[2]) continue;
+            const int64_t q = ((int64_t)z * G.g[1] + y) * G.g[0] + x;
+            if (ranks_above(keys[q], q, kg, g)) bits |= 1u << t;
+        }
+        state[g] = in ? 0 : 3;
+        above[g] = bits;
+    }
+    const uint64_t b = __ballot(in);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&ctr[EX_N_IN],
+                                                 (unsigned long long)__popcll(b));
+}
+
+// One round launch (see above); open candidates left after it are counted
+// into ctr[EX_OPEN + parity], and the other parity's counter is cleared for
+// the next launch.
+__global__ __launch_bounds__(256) void k_ex_round(BoxGrid G, ExDirs D,
+                                                  uint8_t *__restrict__ state,
+                                                  const uint32_t *__restrict__ above, int parity,
+                                                  int64_t *__restrict__ ctr) {
+    constexpr int TN = EXT * EXT * EXT, PER = TN / 256;
+    __shared__ uint8_t ts[TN];
+    __shared__ int s_changed;
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * EXT, y0 = blockIdx.y * EXT, z0 = blockIdx.z * EXT;
+    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0)
+        ctr[EX_OPEN + (parity ^ 1)] = 0;
+    int64_t gi[PER];
+    int lx[PER], ly[PER], lz[PER];
+    bool live[PER];
+    uint32_t ab[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = tid + 256 * p;
+        lx[p] = e % EXT;
+        ly[p] = (e / EXT) % EXT;
+        lz[p] = e / (EXT * EXT);
+        const int x = x0 + lx[p], y = y0 + ly[p], z = z0 + lz[p];
+        live[p] = x < gx && y < gy && z < gz;
+        gi[p] = live[p] ? ((int64_t)z * gy + y) * gx + x : 0;
+        ts[e] = live[p] ? state[gi[p]] : 3;
+        ab[p] = live[p] ? above[gi[p]] : 0;
+    }
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) s_changed = 0;
+        __syncthreads();
+        int changed = 0;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int e = tid + 256 * p;
+            if (ts[e] != 0) continue;
+            bool any_taken = false, all_out = true;
+            uint32_t bits = ab[p];
+            while (bits) {
+                const int t = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int ax = lx[p] + D.dx[t], ay = ly[p] + D.dy[t], az = lz[p] + D.dz[t];
+                uint8_t sq;
+                if (ax >= 0 && ay >= 0 && az >= 0 && ax < EXT && ay < EXT && az < EXT)
+                    sq = ts[(az * EXT + ay) * EXT + ax];
+                else  // outside the tile (inside the grid: only those are flagged)
+                    sq = state[gi[p] + ((int64_t)D.dz[t] * gy + D.dy[t]) * gx + D.dx[t]];
+                any_taken |= sq == 1;
+                all_out &= sq >= 2;
+            }
+            if (any_taken || all_out) {
+                ts[e] = any_taken ? 2 : 1;
+                changed = 1;
+            }
+        }
+        if (changed) s_changed = 1;
+        __syncthreads();
+        if (!s_changed) break;
+        __syncthreads();
+    }
+    int open = 0;
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int e = tid + 256 * p;
+        if (live[p]) state[gi[p]] = ts[e];
+        open += live[p] && ts[e] == 0;
+    }
+    for (int off = 32; off > 0; off >>= 1) open += __shfl_xor(open, off);
+    if ((tid & 63) == 0 && open) atomicAdd((unsigned long long *)&ctr[EX_OPEN + parity],
+                                           (unsigned long long)open);
+}
+
+// Keys remapped for the final select (taken: key + 1, other: 0) and the taken
+// candidates counted into ctr[EX_TAKEN].
+__global__ __launch_bounds__(256) void k_ex_count(uint64_t *__restrict__ keys, int64_t n,
+                                                  const uint8_t *__restrict__ state,
+                                                  int64_t *__restrict__ ctr) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool taken = g < n && state[g] == 1;
+    if (g < n) keys[g] = taken ? keys[g] + 1 : 0;
+    const uint64_t b = __ballot(taken);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&ctr[EX_TAKEN],
+                                                 (unsigned long long)__popcll(b));
+}
+
+// K from the count rule over the candidates inside the mask, then the number
+// kept: min(K, taken).
+__global__ void k_ex_want(double fraction, int64_t *__restrict__ ctr, int64_t *__restrict__ k_out) {
+    if (threadIdx.x != 0) return;
+    const int64_t n_in = ctr[EX_N_IN];
+    const double kd = floor(0.5 + (double)n_in * fraction);
+    const int64_t k = kd < 0 ? 0 : (kd > (double)n_in ? n_in : (int64_t)kd);
+    const int64_t want = k < ctr[EX_TAKEN] ? k : ctr[EX_TAKEN];
+    ctr[EX_WANT] = want;
+    *k_out = want;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Batched selection for small candidate grids.  The keys of every set's
@@ -697,13 +882,61 @@ hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims
                             const uint8_t *mask, int32_t connectivity, int32_t *centers,
                             int64_t *k_device, void *workspace, hipStream_t stream) {
     const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    const BoxGrid G = cubic_grid(block, stride, grid);
+    if (n > kSelectExCand)
+        return launch_select_ex_large(vol, dtype, dims, G, fraction, mask, connectivity, centers,
+                                      k_device, workspace, stream);
     SelectLayout L = select_layout(n);
     uint64_t *keys = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + L.keys_off);
-    const BoxGrid G = cubic_grid(block, stride, grid);
     launch_keys(vol, dtype, dims, G, n, keys, stream);
     hipLaunchKernelGGL(k_select_ex, dim3(1), dim3(1024), 0, stream, keys, n, grid[0], grid[1],
                        grid[2], stride, (block - 1) / 2, dims[0], dims[1], mask, connectivity,
                        fraction, centers, k_device);
+    return hipGetLastError();
+}
+
+// Large grids: round launches until no candidate is open.  The host reads the
+// open count after each launch (a wait on the stream), so this path does not
+// return before its selection is done.
+hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                  const BoxGrid &G, double fraction, const uint8_t *mask,
+                                  int32_t connectivity, int32_t *centers, int64_t *k_device,
+                                  void *workspace, hipStream_t stream) {
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
+    const SelectLayout L = select_layout(n, true);
+    char *ws = static_cast<char *>(workspace);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys_off);
+    int64_t *ctr = reinterpret_cast<int64_t *>(ws + L.ex_ctr_off);
+    uint8_t *state = reinterpret_cast<uint8_t *>(ws + L.ex_state_off);
+    uint32_t *above = reinterpret_cast<uint32_t *>(ws + L.ex_above_off);
+    // page-locked slot for the open count, one per host thread
+    thread_local int64_t *open_h = nullptr;
+    if (!open_h) {
+        void *p = nullptr;
+        if (hipHostMalloc(&p, 64, hipHostMallocDefault) != hipSuccess) return hipErrorOutOfMemory;
+        open_h = static_cast<int64_t *>(p);
+    }
+    const ExDirs D = ex_dirs(connectivity);
+    launch_keys(vol, dtype, dims, G, n, keys, stream);
+    hipLaunchKernelGGL(k_ex_zero, dim3(1), dim3(256), 0, stream, ctr);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_ex_init, dim3(blocks), dim3(256), 0, stream, keys, G, dims[0], dims[1],
+                       mask, D, state, above, ctr);
+    const dim3 tiles((G.g[0] + EXT - 1) / EXT, (G.g[1] + EXT - 1) / EXT, (G.g[2] + EXT - 1) / EXT);
+    // each launch settles at least one candidate, so n launches always end it
+    for (int64_t round = 0; round < n + 1; ++round) {
+        const int parity = (int)(round & 1);
+        hipLaunchKernelGGL(k_ex_round, tiles, dim3(256), 0, stream, G, D, state, above, parity,
+                           ctr);
+        hipError_t e = hipMemcpyAsync(open_h, ctr + EX_OPEN + parity, sizeof(int64_t),
+                                      hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        if (*open_h == 0) break;
+    }
+    hipLaunchKernelGGL(k_ex_count, dim3(blocks), dim3(256), 0, stream, keys, n, state, ctr);
+    hipLaunchKernelGGL(k_ex_want, dim3(1), dim3(64), 0, stream, fraction, ctr, k_device);
+    select_from_keys(keys, n, G, 0, ctr + EX_WANT, centers, L, ws, stream);
     return hipGetLastError();
 }
 
@@ -718,13 +951,20 @@ void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const 
                            stream, static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
 }
 
-SelectLayout select_layout(int64_t n_candidates) {
+SelectLayout select_layout(int64_t n_candidates, bool variants) {
     SelectLayout L;
     L.n_tiles = (n_candidates + kSelectTile - 1) / kSelectTile;
     L.keys_off = 0;
     L.state_off = align_up((size_t)n_candidates * sizeof(uint64_t), 256);
     L.tiles_off = L.state_off + 256;
     L.total = L.tiles_off + align_up((size_t)L.n_tiles * 2 * sizeof(int64_t), 256);
+    // the selection variants on grids of more than kSelectExCand candidates:
+    // a state byte and a ranked-above mask per candidate, four counters
+    L.ex_ctr_off = L.total;
+    L.ex_state_off = L.ex_ctr_off + 256;
+    L.ex_above_off = L.ex_state_off + align_up((size_t)n_candidates, 256);
+    if (variants && n_candidates > kSelectExCand)
+        L.total = L.ex_above_off + align_up((size_t)n_candidates * 4, 256);
     return L;
 }
 
@@ -738,6 +978,20 @@ BoxGrid cubic_grid(int32_t block, int32_t stride, const int32_t grid[3]) {
     return G;
 }
 
+// The K best keys' candidates (key descending, grid index ascending among
+// equal keys) as centres in ascending grid index; K = k, or *kd when given.
+void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t k,
+                      const int64_t *kd, int32_t *centers, const SelectLayout &L, char *ws,
+                      hipStream_t stream) {
+    SelectState *st = reinterpret_cast<SelectState *>(ws + L.state_off);
+    int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
+    hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st);
+    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
+                       st, tiles);
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
+                       tiles, G, k, kd, centers);
+}
+
 hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                          const BoxGrid &G, int64_t k, int32_t *centers, void *workspace,
                          hipStream_t stream) {
@@ -745,14 +999,8 @@ hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3]
     SelectLayout L = select_layout(n);
     char *ws = static_cast<char *>(workspace);
     uint64_t *keys = reinterpret_cast<uint64_t *>(ws + L.keys_off);
-    SelectState *st = reinterpret_cast<SelectState *>(ws + L.state_off);
-    int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
     launch_keys(vol, dtype, dims, G, n, keys, stream);
-    hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, st);
-    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
-                       st, tiles);
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
-                       tiles, G, k, centers);
+    select_from_keys(keys, n, G, k, nullptr, centers, L, ws, stream);
     return hipGetLastError();
 }
 

@@ -206,8 +206,15 @@ def test_select_ex_validation(lib):
                   ctypes.c_void_p]
     assert f(p, 0, dims, 7, 7, 0.2, None, 5, p, 1000, p, p, 1 << 30, None) == 1  # bad pattern
     assert f(p, 0, dims, 7, 7, 1.5, None, 6, p, 1000, p, p, 1 << 30, None) == 1  # bad fraction
-    assert f(p, 0, dims, 3, 1, 0.2, None, 6, p, 10 ** 6, p, p, 1 << 30, None) == 4  # 62^3 cands
+    big = (ctypes.c_int32 * 3)(1302, 1302, 1302)  # block 3, stride 1: 2.2e9 candidates
+    assert f(p, 0, big, 3, 1, 0.2, None, 6, p, 10 ** 6, p, p, 1 << 30, None) == 4
     assert f(p, 0, dims, 7, 7, 0.2, None, 6, p, 1, p, p, 1 << 30, None) == 2  # capacity
+    # large grids (62^3 candidates) need the variants' extra workspace
+    need = nrr.select_workspace_bytes((64, 64, 64), 3, 1)
+    plain = nrr.select_workspace_bytes((64, 64, 64), 3, 3)
+    assert need >= 62 ** 3 * (8 + 5)
+    assert f(p, 0, dims, 3, 1, 0.2, None, 6, p, 10 ** 6, p, p, need - 256, None) == 2
+    assert plain >= 21 ** 3 * 8  # 9,261 candidates: no extra
 
 
 def test_structure_confidence_validation(lib):

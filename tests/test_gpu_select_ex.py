@@ -85,3 +85,59 @@ def test_plain_special_case_equals_select_blocks(torch_dev):
     a = to_host(nrr.select_blocks(to_dev(p.ref), 7, 7, 0.2))
     b = gpu_ex(p.ref, 7, 7, 0.2, None, 0)
     assert np.array_equal(a, b)
+
+
+# Grids above 24,576 candidates take the round-launch path.
+@pytest.mark.parametrize("conn", [0, 6, 18, 26])
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_large_grids_every_pattern(torch_dev, conn, dtype):
+    p = synth.gen_random(50, (66, 60, 52), dtype, smooth=1.5)  # b 3, stride 1: 184,800
+    rng = np.random.default_rng(7)
+    for mask in (None, (rng.random(p.ref.shape) < 0.8).astype(np.uint8)):
+        for b, s, f in [(3, 1, 0.3), (5, 2, 0.9)]:
+            say("select_ex large", dtype, conn, mask is not None, b, s, f)
+            want, _ = oracle.select_ex(p.ref, b, s, f, mask, conn)
+            got = gpu_ex(p.ref, b, s, f, mask, conn)
+            assert np.array_equal(got, want), (dtype, conn, b, s, f)
+
+
+def test_large_grid_with_long_decision_chains(torch_dev):
+    """Block variance rising along x and y (a checkerboard of growing
+    amplitude): every candidate's decision waits for its neighbour's, so the
+    chains run across the whole grid and through many tiles."""
+    nz, ny, nx = 12, 90, 300
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx]
+    vol = (((x + y + z) % 2) * (10 * x + 3 * y + 1)).astype(np.uint16)
+    vol = np.minimum(vol, 4095).astype(np.uint16)
+    for conn in (6, 26):
+        say("select_ex chains", conn)
+        want, _ = oracle.select_ex(vol, 3, 1, 1.0, None, conn)
+        got = gpu_ex(vol, 3, 1, 1.0, None, conn)
+        assert len(want) > 1000
+        assert np.array_equal(got, want), conn
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_dense_grid_with_region_mask(torch_dev, conn):
+    """The dense 512x512x256 workload's grid (9^3 blocks, stride 5: 510,050
+    candidates), a region mask and a pattern, against the oracle."""
+    import time
+
+    import torch
+
+    p = synth.gen_blobs_u16(seed=0)
+    nz, ny, nx = p.ref.shape
+    z, y, x = np.ogrid[0:nz, 0:ny, 0:nx]
+    mask = (((x - nx / 2) / (0.42 * nx)) ** 2 + ((y - ny / 2) / (0.45 * ny)) ** 2 +
+            ((z - nz / 2) / (0.48 * nz)) ** 2 <= 1.0).astype(np.uint8)
+    say("select_ex dense", conn)
+    want, _ = oracle.select_ex(p.ref, 9, 5, 0.7, mask, conn)
+    ref, md = to_dev(p.ref), to_dev(mask)
+    nrr.select_blocks_ex(ref, 9, 5, 0.7, md, conn)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    c = nrr.select_blocks_ex(ref, 9, 5, 0.7, md, conn)
+    torch.cuda.synchronize()
+    say("select_ex dense %d: %d taken, %.2f ms" % (conn, len(c), (time.perf_counter() - t) * 1e3))
+    assert len(want) > 10000  # 6: about 77,000; 26: about 19,000
+    assert np.array_equal(to_host(c), want)
