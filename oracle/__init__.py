@@ -66,6 +66,8 @@ def _load():
         lib.oracle_grid_shape.argtypes = [P, i32, i32, P]
         lib.oracle_select_aniso.restype = i64
         lib.oracle_select_aniso.argtypes = [P, ctypes.c_int, P, P, P, f64, P, P, i64]
+        lib.oracle_select_aniso_ex.restype = i64
+        lib.oracle_select_aniso_ex.argtypes = [P, ctypes.c_int, P, P, P, f64, P, i32, P, P, i64]
         lib.oracle_match_aniso.restype = ctypes.c_int
         lib.oracle_match_aniso.argtypes = [P, P, ctypes.c_int, P, P, i64, P, P, P, P, P]
         lib.oracle_ncc_aniso_at.restype = ctypes.c_int
@@ -217,6 +219,33 @@ def select_aniso(vol: np.ndarray, block, stride, fraction: float):
     if k < 0:
         raise ValueError("oracle_select_aniso rejected the arguments (%d)" % k)
     return centers[:k], var[:k]
+
+
+def select_aniso_ex(vol: np.ndarray, block, stride, fraction: float, mask=None,
+                    connectivity: int = 0):
+    """Selection variants (mask, connectivity pattern) with per-axis block
+    edges and strides: centres int32[k, 3] in ascending grid index and their
+    FP64 variances."""
+    vol, dt = _vol(vol)
+    dims = _dims(vol)
+    b, s = _triple(block), _triple(stride)
+    if np.any(b < 1) or np.any(b % 2 == 0) or np.any(s < 1) or np.any(dims < b):
+        raise ValueError("bad per-axis block/stride")
+    n = int(np.prod((dims - b) // s + 1))
+    cap = max(n, 1)
+    centers = np.zeros((cap, 3), dtype=np.int32)
+    var = np.zeros(cap, dtype=np.float64)
+    mp = None
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert mask.shape == vol.shape
+        mp = _ptr(mask)
+    k = _load().oracle_select_aniso_ex(_ptr(vol), dt, _ptr(dims), _ptr(b), _ptr(s),
+                                       float(fraction), mp, int(connectivity), _ptr(centers),
+                                       _ptr(var), cap)
+    if k < 0:
+        raise ValueError("oracle_select_aniso_ex rejected the arguments (%d)" % k)
+    return centers[:k].copy(), var[:k].copy()
 
 
 def match_aniso(ref: np.ndarray, flt: np.ndarray, centers: np.ndarray, block, window):

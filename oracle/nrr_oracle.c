@@ -596,6 +596,86 @@ int64_t oracle_select_aniso(const void *vol, int dtype, const int32_t dims[3],
     return k;
 }
 
+/*
+ * Selection variants with per-axis sizes: the region restriction and the
+ * connectivity patterns of the "Parallel feature selection" paragraph on the
+ * candidate grid of per-axis block edges b[3] and strides stride[3].  The
+ * mask is read at each candidate's centre (origin + (b[a] - 1) / 2 per
+ * axis), N counts the candidates inside it, K = floor(0.5 + N * fraction);
+ * candidates are visited in rank order (key descending, grid index
+ * ascending) and one is taken unless a grid neighbour (one step along one
+ * axis for 6, along at most two axes for 18, up to three for 26) is already
+ * taken; the visit stops at K taken.  Output as oracle_select_ex.
+ */
+int64_t oracle_select_aniso_ex(const void *vol, int dtype, const int32_t dims[3],
+                               const int32_t b[3], const int32_t stride[3], double fraction,
+                               const uint8_t *mask, int32_t connectivity, int32_t *out_centers,
+                               double *out_var, int64_t capacity) {
+    int32_t grid[3];
+    if (!aniso_sizes_ok(dims, b, stride, grid)) return -1;
+    if (!(fraction > 0.0) || fraction > 1.0) return -1;
+    if (connectivity != 0 && connectivity != 6 && connectivity != 18 && connectivity != 26)
+        return -1;
+    /* axes a neighbour may step along: faces 1, faces and edges 2, all 3 */
+    const int max_steps = connectivity == 6 ? 1 : connectivity == 18 ? 2 : connectivity == 26 ? 3 : 0;
+    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
+    const int64_t plane = (int64_t)grid[0] * grid[1];
+    double *var = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    ranked_t *all = (ranked_t *)malloc(sizeof(ranked_t) * (n > 0 ? n : 1));
+    ranked_t *r = (ranked_t *)malloc(sizeof(ranked_t) * (n > 0 ? n : 1));
+    unsigned char *taken = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int64_t *chosen = (int64_t *)malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t g = 0; g < n; ++g) {
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1], gz = g / plane;
+        aniso_block_variance(vol, dtype, dims, b, gx * stride[0], gy * stride[1], gz * stride[2],
+                             &all[g].key, &var[g]);
+        all[g].idx = g;
+    }
+    int64_t m = 0;
+    for (int64_t g = 0; g < n; ++g) {
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1], gz = g / plane;
+        const int64_t cx = gx * stride[0] + (b[0] - 1) / 2, cy = gy * stride[1] + (b[1] - 1) / 2,
+                      cz = gz * stride[2] + (b[2] - 1) / 2;
+        if (mask && !mask[(cz * dims[1] + cy) * (int64_t)dims[0] + cx]) continue;
+        r[m++] = all[g];
+    }
+    const int64_t k = oracle_select_count(m, fraction);
+    if (k > capacity) {
+        free(var), free(all), free(r), free(taken), free(chosen);
+        return -2;
+    }
+    qsort(r, (size_t)m, sizeof(ranked_t), cmp_rank);
+    int64_t got = 0;
+    for (int64_t i = 0; i < m && got < k; ++i) {
+        const int64_t g = r[i].idx;
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1], gz = g / plane;
+        int blocked = 0;
+        for (int j = 0; j < 27 && !blocked; ++j) {
+            const int dx = j % 3 - 1, dy = (j / 3) % 3 - 1, dz = j / 9 - 1;
+            const int steps = (dx != 0) + (dy != 0) + (dz != 0);
+            if (steps == 0 || steps > max_steps) continue;
+            const int64_t x = gx + dx, y = gy + dy, z = gz + dz;
+            if (x < 0 || y < 0 || z < 0 || x >= grid[0] || y >= grid[1] || z >= grid[2]) continue;
+            blocked = taken[z * plane + y * grid[0] + x];
+        }
+        if (blocked) continue;
+        taken[g] = 1;
+        chosen[got++] = g;
+    }
+    qsort(chosen, (size_t)got, sizeof(int64_t), cmp_i64);
+    for (int64_t i = 0; i < got; ++i) {
+        const int64_t g = chosen[i];
+        const int64_t gx = g % grid[0], gy = (g / grid[0]) % grid[1], gz = g / plane;
+        out_centers[3 * i + 0] = (int32_t)(gx * stride[0] + (b[0] - 1) / 2);
+        out_centers[3 * i + 1] = (int32_t)(gy * stride[1] + (b[1] - 1) / 2);
+        out_centers[3 * i + 2] = (int32_t)(gz * stride[2] + (b[2] - 1) / 2);
+        if (out_var) out_var[i] = var[g];
+    }
+    free(var), free(all), free(r), free(taken), free(chosen);
+    return got;
+}
+
 /* Pearson correlation of the ref block at lowest corner (rx,ry,rz) and the
    flt block at (fx,fy,fz), both bx*by*bz, two-pass FP64; 0 if either is flat. */
 static double aniso_ncc(const void *ref, const void *flt, int dtype, const int32_t dims[3],

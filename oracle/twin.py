@@ -184,6 +184,45 @@ def select_aniso(vol: np.ndarray, block, stride, fraction: float) -> np.ndarray:
                     axis=1).astype(np.int32)
 
 
+def select_aniso_ex(vol: np.ndarray, block, stride, fraction: float, mask=None,
+                    connectivity: int = 0) -> np.ndarray:
+    """Per-axis sizes with a candidate mask and a connectivity pattern: rank
+    every candidate, keep those whose centre the mask allows, then walk the
+    ranking and skip any candidate with a taken grid neighbour (small grids
+    only; a set of taken grid coordinates)."""
+    bx, by, bz = (int(v) for v in block)
+    sx, sy, sz = (int(v) for v in stride)
+    nz, ny, nx = vol.shape
+    ox, oy, oz = grid_origins(nx, bx, sx), grid_origins(ny, by, sy), grid_origins(nz, bz, sz)
+    blocks = sliding_window_view(vol, (bz, by, bx))[np.ix_(oz, oy, ox)]
+    score = blocks.reshape(len(oz), len(oy), len(ox), -1)
+    if vol.dtype == np.uint16:
+        v = score.astype(np.int64)
+        score = bx * by * bz * (v * v).sum(axis=-1) - v.sum(axis=-1) ** 2
+    else:
+        score = score.astype(np.float64).var(axis=-1)
+    cz, cy, cx = np.meshgrid(oz + (bz - 1) // 2, oy + (by - 1) // 2, ox + (bx - 1) // 2,
+                             indexing="ij")
+    inside = np.ones(score.shape, bool) if mask is None else mask[cz, cy, cx] != 0
+    order = np.lexsort((np.arange(score.size), -score.ravel()))
+    order = order[inside.ravel()[order]]
+    k = min(len(order), max(0, math.floor(0.5 + len(order) * fraction)))
+    reach = {0: 0, 6: 1, 18: 2, 26: 3}[connectivity]
+    steps = [(a, b_, c) for a in (-1, 0, 1) for b_ in (-1, 0, 1) for c in (-1, 0, 1)
+             if 0 < abs(a) + abs(b_) + abs(c) <= reach]
+    taken = set()
+    for g in order:
+        if len(taken) == k:
+            break
+        iz, iy, ix = np.unravel_index(g, score.shape)
+        if any((iz + a, iy + b_, ix + c) in taken for a, b_, c in steps):
+            continue
+        taken.add((int(iz), int(iy), int(ix)))
+    out = sorted(taken)  # (z, y, x) order = ascending grid index
+    return np.asarray([(ox[x] + (bx - 1) // 2, oy[y] + (by - 1) // 2, oz[z] + (bz - 1) // 2)
+                       for z, y, x in out], dtype=np.int32).reshape(-1, 3)
+
+
 def match_aniso(ref: np.ndarray, flt: np.ndarray, centers, block, window):
     """Search with per-axis block edges and half windows: every valid shift's
     Pearson correlation, argmax by (largest NCC, smallest shift index)."""

@@ -73,13 +73,23 @@ MUTANTS_ANISO = {
         "if (v > best) {\n                        best = v;\n                        bd[0]",
         "if (v >= best) {\n                        best = v;\n                        bd[0]"),
 }
+# mistakes in the variants with per-axis sizes
+MUTANTS_ANISO_EX = {
+    "aniso_ex_edges_counted_as_vertices": ("connectivity == 18 ? 2 :", "connectivity == 18 ? 3 :"),
+    "aniso_ex_mask_at_y_origin": ("cy = gy * stride[1] + (b[1] - 1) / 2,", "cy = gy * stride[1],"),
+    "aniso_ex_z_neighbours_skipped": ("dz = j / 9 - 1;", "dz = (j / 9 - 1) * 0;"),
+    "aniso_ex_mask_ignored": ("        if (mask && !mask[(cz * dims[1] + cy) * (int64_t)dims[0] + cx]) continue;\n        r[m++] = all[g];",
+                              "        r[m++] = all[g];"),
+}
 PIN_FILES = {name: "test_oracle_pins.py" for name in MUTANTS}
+PIN_FILES.update({name: "test_oracle_select_ex.py" for name in MUTANTS_ANISO_EX})
 PIN_FILES.update({name: "test_oracle_aniso.py" for name in MUTANTS_ANISO})
 PIN_FILES.update({name: "test_oracle_confidence.py" for name in MUTANTS_CONF})
 PIN_FILES.update({name: "test_oracle_select_ex.py" for name in MUTANTS_EX})
 MUTANTS.update(MUTANTS_EX)
 MUTANTS.update(MUTANTS_CONF)
 MUTANTS.update(MUTANTS_ANISO)
+MUTANTS.update(MUTANTS_ANISO_EX)
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

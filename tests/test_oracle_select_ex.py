@@ -112,3 +112,80 @@ def test_mask_count_rule():
     n_in = int((centres_x < 10).sum()) * G[1] * G[2]
     assert len(c) == oracle.select_count(n_in, f)
     assert (c[:, 0] < 10).all()
+
+
+# ---- the variants with per-axis block edges and strides (oracle.select_aniso_ex)
+
+ANISO_SHAPES = [((3, 5, 1), (2, 3, 1), 0.5), ((5, 3, 3), (1, 2, 3), 0.9),
+                ((1, 3, 5), (2, 1, 2), 0.3), ((3, 3, 3), (2, 1, 3), 1.0)]
+
+
+@pytest.mark.parametrize("conn", [0, 6, 18, 26])
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_aniso_twin_agrees(conn, dtype):
+    p = synth.gen_random(31, (17, 14, 12), dtype, smooth=1.0)
+    rng = np.random.default_rng(3)
+    for mask in (None, (rng.random(p.ref.shape) < 0.7).astype(np.uint8)):
+        for b, s, f in ANISO_SHAPES:
+            a, _ = oracle.select_aniso_ex(p.ref, b, s, f, mask, conn)
+            t = twin.select_aniso_ex(p.ref, b, s, f, mask, conn)
+            assert np.array_equal(a, t), (conn, dtype, b, s, f)
+
+
+@pytest.mark.parametrize("conn", [0, 6, 18, 26])
+def test_aniso_equal_sizes_are_the_cubic_variants(conn):
+    """Equal per-axis sizes give what the separately written cubic function
+    gives, with and without a mask."""
+    p = synth.gen_random(32, (20, 17, 15), "u16", smooth=1.2)
+    mask = (np.random.default_rng(4).random(p.ref.shape) < 0.6).astype(np.uint8)
+    for m in (None, mask):
+        for b, s, f in [(3, 2, 0.6), (5, 1, 0.3), (3, 3, 1.0)]:
+            a, va = oracle.select_aniso_ex(p.ref, (b, b, b), (s, s, s), f, m, conn)
+            c, vc = oracle.select_ex(p.ref, b, s, f, m, conn)
+            assert np.array_equal(a, c) and np.array_equal(va, vc), (conn, b, s, f)
+
+
+def test_aniso_plain_rule_is_the_special_case():
+    p = synth.gen_random(33, (19, 16, 13), "f32", smooth=1.0)
+    for b, s, f in ANISO_SHAPES:
+        a, _ = oracle.select_aniso_ex(p.ref, b, s, f, None, 0)
+        c, _ = oracle.select_aniso(p.ref, b, s, f)
+        assert np.array_equal(a, c), (b, s, f)
+
+
+def _row_of_three(amps, along):
+    """A volume of three 3x3x3 blocks in a row along x or z, block i a
+    checkerboard of amplitude amps[i] (its variance rises with it)."""
+    shape = (3, 3, 9) if along == "x" else (9, 3, 3)  # (nz, ny, nx)
+    z, y, x = np.indices(shape)
+    i = (x if along == "x" else z) // 3
+    return (((x + y + z) % 2) * np.asarray(amps)[i]).astype(np.uint16)
+
+
+@pytest.mark.parametrize("along", ["x", "z"])
+def test_aniso_hand_case_neighbours_along_each_axis(along):
+    """Three candidates in a row; the middle one varies most.  With any
+    pattern its two neighbours are blocked; without one all three are taken.
+    Per-axis edges (3, 3, 3) with strides 3 along the row and 1 across it."""
+    vol = _row_of_three((10, 100, 50), along)
+    s = (3, 1, 1) if along == "x" else (1, 1, 3)
+    mid = [4, 1, 1] if along == "x" else [1, 1, 4]
+    for conn in (6, 18, 26):
+        got, _ = oracle.select_aniso_ex(vol, (3, 3, 3), s, 1.0, None, conn)
+        assert got.tolist() == [mid], (along, conn, got)
+    got, _ = oracle.select_aniso_ex(vol, (3, 3, 3), s, 1.0, None, 0)
+    assert len(got) == 3
+
+
+def test_aniso_mask_read_at_the_centre():
+    """The mask is read at the candidate's centre, origin + (edge - 1) / 2 on
+    each axis: a mask of one voxel per allowed block admits exactly those."""
+    p = synth.gen_random(34, (15, 12, 9), "u16", smooth=1.0)
+    b, s = (5, 3, 3), (5, 3, 3)
+    mask = np.zeros(p.ref.shape, dtype=np.uint8)
+    allowed = [(2, 1, 1), (7, 4, 4), (12, 10, 7)]  # centres (x, y, z)
+    for x, y, z in allowed:
+        mask[z, y, x] = 1
+    mask[0, 0, 0] = 1  # a block's corner, not a centre
+    got, _ = oracle.select_aniso_ex(p.ref, b, s, 1.0, mask, 0)
+    assert sorted(map(tuple, got.tolist())) == sorted(allowed)
