@@ -227,9 +227,14 @@ nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype 
  * and outside rules.
  *
  * nrr_aniso_workspace_bytes: device workspace of the selection (grid of
- * block/stride) and of the search (block); either output may be NULL,
- * stride may be NULL (then 1).
+ * block/stride; enough for the variants too) and of the search (block);
+ * either output may be NULL, stride may be NULL (then 1).
+ * nrr_select_count_aniso: the candidate grid (grid may be NULL) and K for
+ * these sizes, on the host.
  * nrr_select_blocks_aniso: as nrr_select_blocks with per-axis sizes.
+ * nrr_select_blocks_aniso_ex: as nrr_select_blocks_ex with per-axis sizes;
+ * the mask is read at each candidate's centre (origin + (edge - 1) / 2 on
+ * each axis) and grid neighbours are one grid step apart along an axis.
  * nrr_block_match_aniso: as nrr_block_match with per-axis sizes; the
  * workspace holds the window statistics of the bx x by x bz block.
  * Errors: INVALID_ARG, UNSUPPORTED (edge or half window above 15, window
@@ -237,11 +242,19 @@ nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype 
 nrr_status nrr_aniso_workspace_bytes(nrr_dtype dtype, const int32_t dims[3],
                                      const int32_t block[3], const int32_t stride[3],
                                      size_t *select_bytes, size_t *match_bytes);
+nrr_status nrr_select_count_aniso(const int32_t dims[3], const int32_t block[3],
+                                  const int32_t stride[3], double fraction, int32_t grid[3],
+                                  int64_t *k);
 nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                    const int32_t block[3], const int32_t stride[3],
                                    double fraction, int32_t *centers, int64_t capacity,
                                    int64_t *k_out, void *workspace, size_t workspace_bytes,
                                    void *stream);
+nrr_status nrr_select_blocks_aniso_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                      const int32_t block[3], const int32_t stride[3],
+                                      double fraction, const uint8_t *mask, int32_t connectivity,
+                                      int32_t *centers, int64_t capacity, int64_t *k_device,
+                                      void *workspace, size_t workspace_bytes, void *stream);
 nrr_status nrr_block_match_aniso(const void *ref, const void *flt, nrr_dtype dtype,
                                  const int32_t dims[3], const int32_t *centers, int64_t n,
                                  const int32_t block[3], const int32_t window[3], int32_t *disp,

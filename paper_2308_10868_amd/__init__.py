@@ -17,7 +17,6 @@ float32) on a HIP device; centres and displacements are ``(x, y, z)`` int32.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 
 __all__ = [
@@ -146,6 +145,9 @@ def load():
         "nrr_aniso_workspace_bytes": (st, [ctypes.c_int, P, P, P, P, P]),
         "nrr_select_blocks_aniso": (st, [P, ctypes.c_int, P, P, P, ctypes.c_double, P, I64, P, P,
                                          ctypes.c_size_t, P]),
+        "nrr_select_count_aniso": (st, [P, P, P, F64, P, P]),
+        "nrr_select_blocks_aniso_ex": (st, [P, ctypes.c_int, P, P, P, F64, P, I32, P, I64, P, P,
+                                            SZ, P]),
         "nrr_block_match_aniso": (st, [P, P, ctypes.c_int, P, P, I64, P, P, P, P, P, P,
                                        ctypes.c_size_t, P]),
         "nrr_block_match_aniso_prepared": (st, [P, P, ctypes.c_int, P, P, I64, P, P, P, P, P, P,
@@ -424,6 +426,14 @@ def aniso_workspace_bytes(dtype, dims, block, stride=None):
     return sb.value, mb.value
 
 
+def select_count_aniso(dims, block, stride, fraction: float) -> int:
+    """K for per-axis sizes (the library's count rule over its grid)."""
+    k = ctypes.c_int64()
+    _check(load().nrr_select_count_aniso(_dims3(dims), _triple(block), _triple(stride),
+                                         float(fraction), None, ctypes.byref(k)))
+    return k.value
+
+
 def select_blocks_aniso(vol, block, stride, fraction: float, workspace=None):
     """Variance-ranked selection with per-axis block edges and strides
     ((x, y, z) triples): int32 [K, 3] centres in ascending grid index."""
@@ -431,9 +441,7 @@ def select_blocks_aniso(vol, block, stride, fraction: float, workspace=None):
     lib = load()
     dt, dims = _vol_info(vol)
     b3, s3 = _triple(block), _triple(stride)
-    grid = [(dims[a] - b3[a]) // s3[a] + 1 for a in range(3)]
-    n = grid[0] * grid[1] * grid[2] if min(grid) > 0 else 0
-    kmax = max(int(math.floor(0.5 + n * fraction)), 1) if n > 0 else 1
+    kmax = max(select_count_aniso(dims, block, stride, fraction), 1)
     out = torch.empty((kmax, 3), dtype=torch.int32, device=vol.device)
     sel_bytes, _ = aniso_workspace_bytes(dt, dims, block, stride)
     ws = _workspace(sel_bytes, vol.device, workspace)
@@ -443,6 +451,33 @@ def select_blocks_aniso(vol, block, stride, fraction: float, workspace=None):
                                        out.shape[0], ctypes.byref(kout),
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(vol)))
     return out[:kout.value]
+
+
+def select_blocks_aniso_ex(vol, block, stride, fraction: float, mask=None,
+                           connectivity: int = 0, workspace=None):
+    """select_blocks_ex with per-axis block edges and strides ((x, y, z)
+    triples).  Synchronises the stream to read k."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(vol)
+    kmax = max(select_count_aniso(dims, block, stride, fraction), 1)
+    out = torch.empty((kmax, 3), dtype=torch.int32, device=vol.device)
+    kd = torch.zeros(1, dtype=torch.int64, device=vol.device)
+    sel_bytes, _ = aniso_workspace_bytes(dt, dims, block, stride)
+    ws = _workspace(sel_bytes, vol.device, workspace)
+    mp = None
+    if mask is not None:
+        if mask.dtype != torch.uint8 or tuple(mask.shape) != tuple(vol.shape) \
+                or not mask.is_contiguous() or mask.device != vol.device:
+            raise NrrError(1, "mask must be a contiguous uint8 tensor shaped like vol")
+        mp = ctypes.c_void_p(mask.data_ptr())
+    _check(lib.nrr_select_blocks_aniso_ex(ctypes.c_void_p(vol.data_ptr()), dt, _dims3(dims),
+                                          _triple(block), _triple(stride), float(fraction), mp,
+                                          int(connectivity), ctypes.c_void_p(out.data_ptr()),
+                                          out.shape[0], ctypes.c_void_p(kd.data_ptr()),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream(vol)))
+    return out[:int(kd.item())]
 
 
 def window_stats_aniso(flt, block, workspace=None):

@@ -486,7 +486,8 @@ nrr_status nrr_aniso_workspace_bytes(nrr_dtype dtype, const int32_t dims[3],
     if (s != NRR_OK) return s;
     nrr::BoxGrid G;
     if ((s = check_box(dims, block, stride, &G)) != NRR_OK) return s;
-    if (select_bytes) *select_bytes = nrr::select_layout((int64_t)G.g[0] * G.g[1] * G.g[2]).total;
+    if (select_bytes)
+        *select_bytes = nrr::select_layout((int64_t)G.g[0] * G.g[1] * G.g[2], true).total;
     if (match_bytes) *match_bytes = nrr::stats_layout(dtype, dims, block, false).total;
     return ok();
 }
@@ -521,6 +522,55 @@ nrr_status nrr_select_blocks_aniso(const void *vol, nrr_dtype dtype, const int32
     return hip_status(nrr::launch_select(vol, dtype, dims, G, k, centers, workspace,
                                          static_cast<hipStream_t>(stream)),
                       "nrr_select_blocks_aniso launch");
+}
+
+nrr_status nrr_select_count_aniso(const int32_t dims[3], const int32_t block[3],
+                                  const int32_t stride[3], double fraction, int32_t grid[3],
+                                  int64_t *k) {
+    if (!stride || !k) return fail(NRR_ERR_INVALID_ARG, "stride and k must be non-NULL");
+    nrr::BoxGrid G;
+    nrr_status s = check_box(dims, block, stride, &G);
+    if (s != NRR_OK) return s;
+    if (!(fraction > 0.0) || fraction > 1.0)
+        return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
+    if (grid)
+        for (int a = 0; a < 3; ++a) grid[a] = G.g[a];
+    *k = count_rule((int64_t)G.g[0] * G.g[1] * G.g[2], fraction);
+    return ok();
+}
+
+nrr_status nrr_select_blocks_aniso_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                                      const int32_t block[3], const int32_t stride[3],
+                                      double fraction, const uint8_t *mask, int32_t connectivity,
+                                      int32_t *centers, int64_t capacity, int64_t *k_device,
+                                      void *workspace, size_t workspace_bytes, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    if (!stride) return fail(NRR_ERR_INVALID_ARG, "stride must be non-NULL");
+    nrr::BoxGrid G;
+    if ((s = check_box(dims, block, stride, &G)) != NRR_OK) return s;
+    if (!(fraction > 0.0) || fraction > 1.0)
+        return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
+    if (connectivity != 0 && connectivity != 6 && connectivity != 18 && connectivity != 26)
+        return fail(NRR_ERR_INVALID_ARG, "connectivity must be 0, 6, 18 or 26 (got %d)",
+                    connectivity);
+    if (!vol || !centers || !k_device || !workspace)
+        return fail(NRR_ERR_INVALID_ARG, "vol, centers, k_device and workspace must be non-NULL");
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
+    if (n >= (1ll << 31))
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (limit 2^31)", (long long)n);
+    const int64_t kmax = count_rule(n, fraction);
+    if (capacity < kmax)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "capacity %lld < %lld", (long long)capacity,
+                    (long long)kmax);
+    const nrr::SelectLayout L = nrr::select_layout(n, true);
+    if (workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
+                    L.total);
+    return hip_status(nrr::launch_select_ex(vol, dtype, dims, G, fraction, mask, connectivity,
+                                            centers, k_device, workspace,
+                                            static_cast<hipStream_t>(stream)),
+                      "nrr_select_blocks_aniso_ex launch");
 }
 
 namespace {

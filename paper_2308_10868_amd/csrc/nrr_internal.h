@@ -53,6 +53,10 @@ hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims
                             int32_t block, int32_t stride, const int32_t grid[3], double fraction,
                             const uint8_t *mask, int32_t connectivity, int32_t *centers,
                             int64_t *k_device, void *workspace, hipStream_t stream);
+hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            const BoxGrid &G, double fraction, const uint8_t *mask,
+                            int32_t connectivity, int32_t *centers, int64_t *k_device,
+                            void *workspace, hipStream_t stream);
 hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                   const BoxGrid &G, double fraction, const uint8_t *mask,
                                   int32_t connectivity, int32_t *centers, int64_t *k_device,

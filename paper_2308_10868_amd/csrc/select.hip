@@ -393,8 +393,7 @@ __device__ inline bool ranks_above(uint64_t ka, int64_t ia, uint64_t kb, int64_t
 }
 
 __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__ keys, int64_t n,
-                                                    int gx, int gy, int gz, int stride, int h,
-                                                    int nx, int ny,
+                                                    BoxGrid G, int nx, int ny,
                                                     const uint8_t *__restrict__ mask,
                                                     int connectivity, double fraction,
                                                     int32_t *__restrict__ centers,
@@ -410,6 +409,7 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_need;
     const int tid = threadIdx.x;
+    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
     // neighbours of the pattern: one, up to two, or up to three axis steps
     const int max_steps = connectivity == 6 ? 1 : (connectivity == 18 ? 2 : (connectivity == 26 ? 3 : 0));
     if (tid < 26) {
@@ -439,7 +439,9 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
         const int iz = g / gxy, r = g - iz * gxy, iy = r / gx, ix = r - iy * gx;
         bool in = true;
         if (mask)
-            in = mask[((int64_t)(iz * stride + h) * ny + (iy * stride + h)) * nx + (ix * stride + h)] != 0;
+            in = mask[((int64_t)(iz * G.s[2] + (G.b[2] - 1) / 2) * ny +
+                       (iy * G.s[1] + (G.b[1] - 1) / 2)) * nx +
+                      (ix * G.s[0] + (G.b[0] - 1) / 2)] != 0;
         state[g] = in ? 0 : 3;
         in_local += in;
         uint32_t bits = 0;
@@ -552,9 +554,9 @@ __global__ __launch_bounds__(1024) void k_select_ex(const uint64_t *__restrict__
             const int64_t pos = gt_before + (eq_before < take_eq ? eq_before : take_eq);
             const int gi = (int)g, iz = gi / (gx * gy), r = gi - iz * gx * gy, iy = r / gx,
                       ix = r - iy * gx;
-            centers[3 * pos + 0] = (int32_t)(ix * stride + h);
-            centers[3 * pos + 1] = (int32_t)(iy * stride + h);
-            centers[3 * pos + 2] = (int32_t)(iz * stride + h);
+            centers[3 * pos + 0] = (int32_t)(ix * G.s[0] + (G.b[0] - 1) / 2);
+            centers[3 * pos + 1] = (int32_t)(iy * G.s[1] + (G.b[1] - 1) / 2);
+            centers[3 * pos + 2] = (int32_t)(iz * G.s[2] + (G.b[2] - 1) / 2);
         }
         gt_before += is_gt;
         eq_before += is_eq;
@@ -881,17 +883,23 @@ hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims
                             int32_t block, int32_t stride, const int32_t grid[3], double fraction,
                             const uint8_t *mask, int32_t connectivity, int32_t *centers,
                             int64_t *k_device, void *workspace, hipStream_t stream) {
-    const int64_t n = (int64_t)grid[0] * grid[1] * grid[2];
-    const BoxGrid G = cubic_grid(block, stride, grid);
+    return launch_select_ex(vol, dtype, dims, cubic_grid(block, stride, grid), fraction, mask,
+                            connectivity, centers, k_device, workspace, stream);
+}
+
+hipError_t launch_select_ex(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            const BoxGrid &G, double fraction, const uint8_t *mask,
+                            int32_t connectivity, int32_t *centers, int64_t *k_device,
+                            void *workspace, hipStream_t stream) {
+    const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
     if (n > kSelectExCand)
         return launch_select_ex_large(vol, dtype, dims, G, fraction, mask, connectivity, centers,
                                       k_device, workspace, stream);
     SelectLayout L = select_layout(n);
     uint64_t *keys = reinterpret_cast<uint64_t *>(static_cast<char *>(workspace) + L.keys_off);
     launch_keys(vol, dtype, dims, G, n, keys, stream);
-    hipLaunchKernelGGL(k_select_ex, dim3(1), dim3(1024), 0, stream, keys, n, grid[0], grid[1],
-                       grid[2], stride, (block - 1) / 2, dims[0], dims[1], mask, connectivity,
-                       fraction, centers, k_device);
+    hipLaunchKernelGGL(k_select_ex, dim3(1), dim3(1024), 0, stream, keys, n, G, dims[0], dims[1],
+                       mask, connectivity, fraction, centers, k_device);
     return hipGetLastError();
 }
 

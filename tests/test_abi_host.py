@@ -276,3 +276,23 @@ def test_aniso_validation(lib):
     assert sel(p, 0, dims, t3(5, 3, 7), t3(5, 3, 7), 0.5, p, 1, ctypes.byref(k), p, 1 << 30,
                None) == 2  # capacity
     assert k.value == int(0.5 + 8 * 10 * 2 * 0.5)
+
+
+def test_select_count_aniso_matches_the_rule():
+    import ctypes
+
+    import oracle
+
+    for dims, b, st, f in [((256, 256, 124), (7, 7, 3), (7, 7, 3), 0.25),
+                           ((19, 15, 13), (3, 5, 1), (2, 3, 1), 0.5),
+                           ((64, 64, 64), (9, 1, 5), (4, 1, 5), 0.07)]:
+        k = nrr.select_count_aniso(dims, b, st, f)
+        grid = [(dims[a] - b[a]) // st[a] + 1 for a in range(3)]
+        assert k == oracle.select_count(grid[0] * grid[1] * grid[2], f)
+        g = (ctypes.c_int32 * 3)()
+        kk = ctypes.c_int64()
+        assert nrr.load().nrr_select_count_aniso(nrr._dims3(dims), nrr._triple(b),
+                                                 nrr._triple(st), f, g, ctypes.byref(kk)) == 0
+        assert list(g) == grid and kk.value == k
+    with pytest.raises(nrr.NrrError):
+        nrr.select_count_aniso((10, 10, 10), (4, 3, 3), (1, 1, 1), 0.5)  # even edge

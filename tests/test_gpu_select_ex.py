@@ -141,3 +141,42 @@ def test_dense_grid_with_region_mask(torch_dev, conn):
     say("select_ex dense %d: %d taken, %.2f ms" % (conn, len(c), (time.perf_counter() - t) * 1e3))
     assert len(want) > 10000  # 6: about 77,000; 26: about 19,000
     assert np.array_equal(to_host(c), want)
+
+
+# Per-axis block edges and strides with the variants.
+@pytest.mark.parametrize("conn", [0, 6, 18, 26])
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_aniso_variants_small(torch_dev, conn, dtype):
+    import torch
+
+    p = synth.gen_random(60, (23, 19, 15), dtype, smooth=1.0)
+    rng = np.random.default_rng(8)
+    for mask in (None, (rng.random(p.ref.shape) < 0.7).astype(np.uint8)):
+        for b, s, f in [((3, 5, 1), (2, 3, 1), 0.5), ((5, 3, 3), (1, 2, 3), 0.9),
+                        ((1, 3, 5), (2, 1, 2), 0.3), ((7, 3, 3), (3, 3, 1), 1.0)]:
+            say("select_aniso_ex", dtype, conn, mask is not None, b, s, f)
+            want, _ = oracle.select_aniso_ex(p.ref, b, s, f, mask, conn)
+            c = nrr.select_blocks_aniso_ex(to_dev(p.ref), b, s, f,
+                                           None if mask is None else to_dev(mask), conn)
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host(c), want), (dtype, conn, b, s, f)
+
+
+@pytest.mark.parametrize("conn", [6, 26])
+def test_aniso_variants_mri_slices(torch_dev, conn):
+    """The MRI pair with blocks thinner along the slice axis (7 x 7 x 3,
+    stride 7 x 7 x 3: 53,136 candidates, the round-launch path) inside an
+    ellipsoidal region."""
+    import torch
+
+    p = synth.gen_mri_u16(seed=0)
+    nz, ny, nx = p.ref.shape
+    z, y, x = np.ogrid[0:nz, 0:ny, 0:nx]
+    mask = (((x - nx / 2) / (0.42 * nx)) ** 2 + ((y - ny / 2) / (0.45 * ny)) ** 2 +
+            ((z - nz / 2) / (0.48 * nz)) ** 2 <= 1.0).astype(np.uint8)
+    say("select_aniso_ex mri", conn)
+    want, _ = oracle.select_aniso_ex(p.ref, (7, 7, 3), (7, 7, 3), 0.25, mask, conn)
+    c = nrr.select_blocks_aniso_ex(to_dev(p.ref), (7, 7, 3), (7, 7, 3), 0.25, to_dev(mask), conn)
+    torch.cuda.synchronize()
+    assert len(want) > 1000
+    assert np.array_equal(to_host(c), want)
