@@ -21,9 +21,12 @@ constexpr int kSelectTile = 2048;  // candidates per compaction workgroup
 
 struct SelectLayout {
     size_t keys_off, state_off, tiles_off, total;
+    size_t radix_rows_off;                          // 0: one-workgroup radix select
     size_t ex_ctr_off, ex_state_off, ex_above_off;  // selection variants, large grids
     int64_t n_tiles;
 };
+// Grids of more candidates take the multi-workgroup radix select.
+constexpr int64_t kRadixMultiMin = 1 << 16;
 // variants: room for the selection variants on large grids as well
 SelectLayout select_layout(int64_t n_candidates, bool variants = false);
 

@@ -15,6 +15,8 @@
 // non-negative double is monotone in its value).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "nrr_internal.h"
 
 namespace nrr {
@@ -25,37 +27,122 @@ struct SelectState {
     int64_t take_eq;  // how many candidates with key == kth are kept (lowest indices)
 };
 
-// One wavefront per candidate block: lanes take the block's by*bz rows, sum
-// them exactly in integers and reduce across the wavefront.
+// Wavefronts walk the candidates; a wavefront reads one block with its lanes
+// packed along the block's rows (element e = lane + 64 k in x, y, z order),
+// so a load instruction touches a few consecutive rows rather than 64 of
+// them, sums exactly in integers and reduces across the wavefront.  A lane's
+// element offsets advance by a fixed step with carries (no division per
+// element).  Workgroups are dealt to the 8 XCDs in turn; each XCD takes a
+// contiguous eighth of the candidates and its wavefronts walk it together,
+// so the blocks in flight on an XCD overlap in its L2.
 __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restrict__ vol, int nx,
                                                         int ny, BoxGrid G, int64_t n,
                                                         uint64_t *__restrict__ keys) {
-    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (g >= n) return;  // whole wavefront leaves together
     const int bx = G.b[0], by = G.b[1], bz = G.b[2];
-    // candidate coordinates in 32-bit arithmetic (grids hold < 2^31 candidates)
-    const int gi = (int)g, gxy = G.g[0] * G.g[1];
-    const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
-    const int64_t x0 = (int64_t)ix * G.s[0], y0 = (int64_t)iy * G.s[1], z0 = (int64_t)iz * G.s[2];
-    uint64_t s = 0, q = 0;
-    for (int r = lane; r < by * bz; r += 64) {
-        const int z = r / by, y = r - z * by;
-        const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-        uint32_t rs = 0, rq = 0;  // row sums: <= 15 * 4095^2 < 2^32
-        for (int x = 0; x < bx; ++x) {
-            const uint32_t v = row[x];
-            rs += v;
-            rq += v * v;
+    const int nb = bx * by * bz;
+    const int64_t plane = (int64_t)ny * nx;
+    // the lane's first element and the step of 64 elements
+    const int r0 = lane / bx, x0l = lane - r0 * bx;
+    const int y0l = r0 % by, z0l = r0 / by;
+    const int sx = 64 % bx, sr = 64 / bx;
+    // this workgroup's XCD (dispatch order) and its wavefront among the XCD's
+    const int xcd = blockIdx.x & 7, nx_wg = (int)(gridDim.x >> 3);  // grid: multiple of 8
+    const int64_t waves = (int64_t)nx_wg * 4;
+    const int64_t per = (n + 7) / 8, lo = xcd * per, hi = min(n, lo + per);
+    for (int64_t g = lo + (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); g < hi; g += waves) {
+        // candidate coordinates in 32-bit arithmetic (grids hold < 2^31 candidates)
+        const int gi = (int)g, gxy = G.g[0] * G.g[1];
+        const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
+        const uint16_t *base =
+            vol + ((int64_t)iz * G.s[2] * ny + (int64_t)iy * G.s[1]) * nx + (int64_t)ix * G.s[0];
+        int x = x0l, y = y0l, z = z0l;
+        uint64_t s = 0, q = 0;
+        // chunks of 16 elements per lane: all 16 loads are in flight before
+        // the first is summed
+        for (int e = lane; e < nb; e += 64) {
+            const uint32_t v = base[(int64_t)z * plane + (int64_t)y * nx + x];
+            s += v;
+            q += v * v;
+            x += sx;
+            y += sr;
+            if (x >= bx) {
+                x -= bx;
+                ++y;
+            }
+            while (y >= by) {
+                y -= by;
+                ++z;
+            }
         }
-        s += rs;
-        q += rq;
+        for (int off = 32; off > 0; off >>= 1) {
+            s += __shfl_xor(s, off);
+            q += __shfl_xor(q, off);
+        }
+        if (lane == 0) keys[g] = (uint64_t)nb * q - s * s;  // >= 0 by Cauchy-Schwarz
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        s += __shfl_xor(s, off);
-        q += __shfl_xor(q, off);
+}
+
+// Tiled keys for overlapping candidates (tile regions up to 120 voxels a side): a
+// workgroup takes 16 x 16 candidates in x and y at one candidate plane z.
+// For each of the block's bz voxel planes it stages the tile's region
+// ((15 sx + bx) x (15 sy + by) voxels, rows along x, coalesced) in LDS, forms
+// for every region row the sums over each candidate column's bx voxels, and
+// each thread adds its candidate's by rows of those.  Every voxel of the
+// region is read from L2 once per candidate plane that contains it.
+constexpr int KT = 16, KT_MAXR = 120;  // region edge 15 s + b at most 120
+
+__global__ __launch_bounds__(256) void k_block_keys_u16_tiled(const uint16_t *__restrict__ vol,
+                                                              int nx, int ny, BoxGrid G,
+                                                              uint64_t *__restrict__ keys) {
+    // dynamic LDS: the region [RY][RX] (u16, RX even), then the row sums
+    // [RY][KT] and sums of squares [RY][KT] (u32); RX, RY of a full tile
+    extern __shared__ __align__(16) unsigned char lds_keys[];
+    const int RX = ((KT - 1) * G.s[0] + G.b[0] + 1) & ~1, RY = (KT - 1) * G.s[1] + G.b[1];
+    uint16_t *reg = reinterpret_cast<uint16_t *>(lds_keys);
+    uint32_t *rsum = reinterpret_cast<uint32_t *>(lds_keys + (size_t)RX * RY * 2);
+    uint32_t *rsq = rsum + RY * KT;
+    const int tid = threadIdx.x;
+    const int bx = G.b[0], by = G.b[1], bz = G.b[2];
+    const int cx0 = blockIdx.x * KT, cy0 = blockIdx.y * KT, cz = blockIdx.z;
+    const int ncx = min(KT, G.g[0] - cx0), ncy = min(KT, G.g[1] - cy0);
+    const int rx = (ncx - 1) * G.s[0] + bx, ry = (ncy - 1) * G.s[1] + by;  // region in the volume
+    const int64_t x0 = (int64_t)cx0 * G.s[0], y0 = (int64_t)cy0 * G.s[1];
+    const int64_t z0 = (int64_t)cz * G.s[2];
+    const int i = tid % KT, j = tid / KT;  // this thread's candidate in the tile
+    uint64_t s_acc = 0, q_acc = 0;
+    for (int pz = 0; pz < bz; ++pz) {
+        const uint16_t *pl = vol + ((z0 + pz) * ny + y0) * (int64_t)nx + x0;
+        for (int e = tid; e < rx * ry; e += 256) {
+            const int r = e / rx, c = e - r * rx;
+            reg[r * RX + c] = pl[(int64_t)r * nx + c];
+        }
+        __syncthreads();
+        for (int e = tid; e < ry * ncx; e += 256) {  // row r, candidate column ci
+            const int r = e / ncx, ci = e - r * ncx;
+            const uint16_t *row = reg + r * RX + ci * G.s[0];
+            uint32_t a = 0, b2 = 0;  // bx <= 120 voxels: < 2^32
+            for (int k = 0; k < bx; ++k) {
+                const uint32_t v = row[k];
+                a += v;
+                b2 += v * v;
+            }
+            rsum[r * KT + ci] = a;
+            rsq[r * KT + ci] = b2;
+        }
+        __syncthreads();
+        if (i < ncx && j < ncy) {
+            for (int k = 0; k < by; ++k) {
+                s_acc += rsum[(j * G.s[1] + k) * KT + i];
+                q_acc += rsq[(j * G.s[1] + k) * KT + i];
+            }
+        }
+        __syncthreads();  // the region and the row sums are rewritten next plane
     }
-    if (lane == 0) keys[g] = (uint64_t)bx * by * bz * q - s * s;  // >= 0 by Cauchy-Schwarz
+    if (i < ncx && j < ncy) {
+        const int64_t g = ((int64_t)cz * G.g[1] + cy0 + j) * G.g[0] + cx0 + i;
+        keys[g] = (uint64_t)bx * by * bz * q_acc - s_acc * s_acc;
+    }
 }
 
 // FP64 two-pass variance of the bx*by*bz block at (x0, y0, z0), summed in
@@ -224,6 +311,95 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
         // bytes below `top`+8 were all resolved; bytes above are zero in every key
         st->kth = s_prefix;
         st->take_eq = s_need;
+    }
+}
+
+// Multi-workgroup radix select for large grids: eight passes of one byte,
+// most significant first.  Each pass counts the digits of the keys that
+// match the prefix found so far into one histogram row per workgroup; one
+// workgroup then sums the rows and picks the digit that holds the need-th
+// largest key.  Fixed launches, no host round trip.
+constexpr int kRadixWG = 256;  // workgroups of a histogram pass
+constexpr int kRadixRows = 8;  // histogram rows they add into (spreads the atomics)
+
+struct RadixState {
+    uint64_t prefix, mask;
+    int64_t need;
+};
+
+__global__ __launch_bounds__(256) void k_radix_init(int64_t k, const int64_t *__restrict__ kd,
+                                                    RadixState *__restrict__ rs,
+                                                    uint32_t *__restrict__ rows) {
+    for (int i = threadIdx.x; i < kRadixRows * 256; i += 256) rows[i] = 0;
+    if (threadIdx.x != 0) return;
+    rs->prefix = 0;
+    rs->mask = 0;
+    rs->need = kd ? *kd : k;
+}
+
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n,
+                                                    const RadixState *__restrict__ rs, int shift,
+                                                    uint32_t *__restrict__ rows) {
+    __shared__ uint32_t hist[256];
+    const int tid = threadIdx.x;
+    hist[tid] = 0;
+    __syncthreads();
+    const uint64_t prefix = rs->prefix, mask = rs->mask;
+    const int64_t step = (int64_t)gridDim.x * 256;
+    // uniform trip count per workgroup so the ballots in hist_add converge
+    const int64_t iters = (n + step - 1) / step;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t i = it * step + (int64_t)blockIdx.x * 256 + tid;
+        const uint64_t kv = i < n ? keys[i] : 0;
+        hist_add(hist, (uint32_t)((kv >> shift) & 0xff), i < n && (kv & mask) == prefix);
+    }
+    __syncthreads();
+    if (hist[tid]) atomicAdd(&rows[(blockIdx.x % kRadixRows) * 256 + tid], hist[tid]);
+}
+
+__global__ __launch_bounds__(256) void k_radix_pick(uint32_t *__restrict__ rows, int nrows,
+                                                    int shift, RadixState *__restrict__ rs,
+                                                    SelectState *__restrict__ st) {
+    __shared__ int64_t s_w[4];
+    __shared__ uint64_t s_prefix, s_mask;
+    __shared__ int64_t s_need;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) {
+        s_prefix = rs->prefix;
+        s_mask = rs->mask;
+        s_need = rs->need;
+    }
+    const int d = 255 - tid;  // thread t holds digit 255 - t: descending order
+    int64_t c = 0;
+    for (int r = 0; r < nrows; ++r) {  // read, then cleared for the next pass
+        c += rows[r * 256 + d];
+        rows[r * 256 + d] = 0;
+    }
+    // inclusive scan over the 256 threads
+    int64_t incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) s_w[w] = incl;
+    __syncthreads();
+    for (int i = 0; i < w; ++i) incl += s_w[i];
+    const int64_t need = s_need, above = incl - c;
+    __syncthreads();  // every thread has read s_need before it changes
+    if (above < need && need <= incl) {  // one thread at most
+        s_need = need - above;
+        s_prefix |= (uint64_t)d << shift;
+        s_mask |= 0xffull << shift;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        rs->prefix = s_prefix;
+        rs->mask = s_mask;
+        rs->need = s_need;
+        if (shift == 0) {  // every byte resolved
+            st->kth = s_prefix;
+            st->take_eq = s_need;
+        }
     }
 }
 
@@ -951,9 +1127,21 @@ hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_
 // Ranking keys of every candidate of the grid G.
 void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const BoxGrid &G,
                  int64_t n, uint64_t *keys, hipStream_t stream) {
-    if (dtype == NRR_U16)
-        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
-                           static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n, keys);
+    // overlapping candidates (stride below the edge in x or y) whose tile
+    // region fits: the tiled kernel; otherwise one wavefront per candidate
+    const bool overlap = G.s[0] < G.b[0] || G.s[1] < G.b[1];
+    const int rx = ((KT - 1) * G.s[0] + G.b[0] + 1) & ~1, ry = (KT - 1) * G.s[1] + G.b[1];
+    if (dtype == NRR_U16 && overlap && rx <= KT_MAXR && ry <= KT_MAXR)
+        hipLaunchKernelGGL(k_block_keys_u16_tiled,
+                           dim3((unsigned)((G.g[0] + KT - 1) / KT), (unsigned)((G.g[1] + KT - 1) / KT),
+                                (unsigned)G.g[2]),
+                           dim3(256), (size_t)rx * ry * 2 + (size_t)ry * KT * 8, stream,
+                           static_cast<const uint16_t *>(vol), dims[0], dims[1], G, keys);
+    else if (dtype == NRR_U16)  // wavefronts walk the candidates: 8 workgroups per CU at most
+        hipLaunchKernelGGL(k_block_keys_u16,
+                           dim3((unsigned)(std::min<int64_t>((n + 31) / 32, 256) * 8)), dim3(256),
+                           0, stream, static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n,
+                           keys);
     else
         hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            stream, static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
@@ -966,6 +1154,12 @@ SelectLayout select_layout(int64_t n_candidates, bool variants) {
     L.state_off = align_up((size_t)n_candidates * sizeof(uint64_t), 256);
     L.tiles_off = L.state_off + 256;
     L.total = L.tiles_off + align_up((size_t)L.n_tiles * 2 * sizeof(int64_t), 256);
+    // the multi-workgroup radix select's histogram rows (large grids)
+    L.radix_rows_off = 0;
+    if (n_candidates > kRadixMultiMin) {
+        L.radix_rows_off = L.total;
+        L.total += (size_t)kRadixRows * 256 * 4;
+    }
     // the selection variants on grids of more than kSelectExCand candidates:
     // a state byte and a ranked-above mask per candidate, four counters
     L.ex_ctr_off = L.total;
@@ -993,7 +1187,19 @@ void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t
                       hipStream_t stream) {
     SelectState *st = reinterpret_cast<SelectState *>(ws + L.state_off);
     int64_t *tiles = reinterpret_cast<int64_t *>(ws + L.tiles_off);
-    hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st);
+    if (L.radix_rows_off) {  // large grid: multi-workgroup passes
+        RadixState *rs = reinterpret_cast<RadixState *>(ws + L.state_off + 64);
+        uint32_t *rows = reinterpret_cast<uint32_t *>(ws + L.radix_rows_off);
+        hipLaunchKernelGGL(k_radix_init, dim3(1), dim3(256), 0, stream, k, kd, rs, rows);
+        for (int shift = 56; shift >= 0; shift -= 8) {
+            hipLaunchKernelGGL(k_radix_hist, dim3(kRadixWG), dim3(256), 0, stream, keys, n, rs,
+                               shift, rows);
+            hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(256), 0, stream, rows, kRadixRows,
+                               shift, rs, st);
+        }
+    } else {
+        hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st);
+    }
     hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
                        st, tiles);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,

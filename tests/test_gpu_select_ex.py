@@ -180,3 +180,21 @@ def test_aniso_variants_mri_slices(torch_dev, conn):
     torch.cuda.synchronize()
     assert len(want) > 1000
     assert np.array_equal(to_host(c), want)
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_plain_selection_large_grid_with_ties(torch_dev, dtype):
+    """Grids above 65,536 candidates take the multi-workgroup radix select:
+    half the volume is flat, so thousands of candidates share the key 0 and
+    the K-th key falls among them (ties to the lower grid index)."""
+    import torch
+
+    p = synth.gen_random(70, (120, 100, 90), dtype, smooth=1.0)
+    ref = p.ref.copy()
+    ref[:, :, :60] = ref[0, 0, 0]  # flat half
+    for b, s, f in [(3, 2, 0.7), (5, 1, 0.55), (3, 1, 0.05), (15, 8, 0.3)]:
+        say("plain selection large", dtype, b, s, f)
+        want, _ = oracle.select(ref, b, s, f)
+        got = nrr.select_blocks(to_dev(ref), b, s, f)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(got), want), (dtype, b, s, f)
