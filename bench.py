@@ -248,7 +248,7 @@ def main() -> int:
         # the selection and around the search, all on the main stream.
         side.wait_stream(stream)
         with torch.cuda.stream(side):
-            nrr.window_stats(flt, b, workspace=mat_ws)
+            nrr.window_stats(flt, b, workspace=mat_ws, window=w)
         if ev is not None:
             ev[0].record(stream)
         centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
@@ -298,7 +298,7 @@ def main() -> int:
                 cap = torch.cuda.current_stream()
                 side.wait_stream(cap)
                 with torch.cuda.stream(side):
-                    nrr.window_stats(flt, b, workspace=mat_ws)
+                    nrr.window_stats(flt, b, workspace=mat_ws, window=w)
                 g_centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
                 cap.wait_stream(side)
             torch.cuda.synchronize()

@@ -208,6 +208,15 @@ nrr_status nrr_window_stats(const void *flt, nrr_dtype dtype, const int32_t dims
                             int32_t block, void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* nrr_window_stats_for: as nrr_window_stats, for the search that nrr_block_match_prepared will run
+ * with this window under the current plan (nrr_match_plan): the plane-pair
+ * volume of 12-bit data is written only when that search reads it (the
+ * dot2 form).  If the plan changes before the search (tuning, NRR_ARITH),
+ * the prepared search adds the missing part itself. */
+nrr_status nrr_window_stats_for(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                                int32_t block, int32_t window, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype dtype,
                                     const int32_t dims[3], const int32_t *centers, int64_t n,
                                     int32_t block, int32_t window, int32_t *disp, float *ncc,

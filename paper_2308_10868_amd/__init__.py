@@ -140,6 +140,7 @@ def load():
                                       P]),
         "nrr_select_blocks_static": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P]),
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
+        "nrr_window_stats_for": (st, [P, ctypes.c_int, P, I32, I32, P, SZ, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
         "nrr_aniso_workspace_bytes": (st, [ctypes.c_int, P, P, P, P, P]),
@@ -333,14 +334,21 @@ def select_blocks_ex(vol, block: int, stride: int, fraction: float, mask=None,
     return out[:int(kd.item())]
 
 
-def window_stats(flt, block: int, workspace=None):
+def window_stats(flt, block: int, workspace=None, window=None):
     """Per-voxel window statistics of `flt` for this block size (the table
-    block_match(..., prepared=True) reads).  Returns the workspace tensor."""
+    block_match(..., prepared=True) reads).  With `window`, only what the
+    planned search for that window reads (nrr_window_stats_for).  Returns the
+    workspace tensor."""
     lib = load()
     dt, dims = _vol_info(flt)
     ws = _workspace(match_workspace_bytes(dt, dims, block), flt.device, workspace)
-    _check(lib.nrr_window_stats(ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims), block,
-                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(flt)))
+    if window is None:
+        _check(lib.nrr_window_stats(ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims), block,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(flt)))
+    else:
+        _check(lib.nrr_window_stats_for(ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims), block,
+                                        int(window), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream(flt)))
     return ws
 
 

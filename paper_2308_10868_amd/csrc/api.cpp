@@ -8,7 +8,9 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <numeric>
+#include <unordered_map>
 #include <vector>
 
 #include "nrr.h"
@@ -291,12 +293,46 @@ nrr::MatchArgs match_args(const void *ref, const void *flt, const int32_t dims[3
     return a;
 }
 
+// Whether a search workspace holds the plane-pair volume of 12-bit data (the
+// dot2 form reads it; the other forms do not), as the last statistics call
+// on that workspace left it.  Workspaces never filled by nrr_window_stats_for
+// count as holding it (nrr_window_stats always writes it).
+std::mutex g_pairs_mu;
+std::unordered_map<const void *, bool> g_pairs;
+
+void note_pairs(const void *ws, bool has) {
+    std::lock_guard<std::mutex> lk(g_pairs_mu);
+    if (has)
+        g_pairs.erase(ws);
+    else
+        g_pairs[ws] = false;
+}
+
+bool holds_pairs(const void *ws) {
+    std::lock_guard<std::mutex> lk(g_pairs_mu);
+    return g_pairs.find(ws) == g_pairs.end();
+}
+
+// Does the search planned for these sizes read the plane-pair volume?
+bool plan_reads_pairs(nrr_dtype dtype, const nrr::MatchArgs &a) {
+    if (dtype != NRR_U16) return false;
+    nrr::TileShape t;
+    return !nrr::match_plan(dtype, a, &t) || t.arith == 0;
+}
+
 nrr_status run_match(const void *ref, const void *flt, nrr_dtype dtype, const int32_t dims[3],
                      const int32_t *centers, int64_t n, int32_t block, int32_t window,
                      int32_t *disp, float *ncc, float *conf, const void *workspace,
                      const nrr::StatsLayout &L, hipStream_t st) {
     const nrr::MatchArgs a =
         match_args(ref, flt, dims, centers, n, block, window, disp, ncc, conf, workspace, L);
+    if (L.pair_off && plan_reads_pairs(dtype, a) && !holds_pairs(workspace)) {
+        // statistics made for another plan: add the pair volume now
+        hipError_t e = nrr::launch_pair_volume(static_cast<const uint16_t *>(flt), dims,
+                                               const_cast<uint32_t *>(a.pairs), st);
+        if (e != hipSuccess) return hip_status(e, "pair volume launch");
+        note_pairs(workspace, true);
+    }
     return hip_status(nrr::launch_match(dtype, a, st), "block match launch");
 }
 
@@ -385,7 +421,32 @@ nrr_status nrr_window_stats(const void *flt, nrr_dtype dtype, const int32_t dims
     if (workspace_bytes < L.total)
         return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
                     L.total);
+    note_pairs(workspace, true);
     return hip_status(nrr::launch_stats(flt, dtype, dims, block, workspace,
+                                        static_cast<hipStream_t>(stream)),
+                      "window statistics launch");
+}
+
+nrr_status nrr_window_stats_for(const void *flt, nrr_dtype dtype, const int32_t dims[3],
+                                int32_t block, int32_t window, void *workspace,
+                                size_t workspace_bytes, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    int32_t g[3];
+    if ((s = check_grid(dims, block, 1, g)) != NRR_OK) return s;
+    if (block > 15) return fail(NRR_ERR_UNSUPPORTED, "block edge above 15 is not built");
+    if (window < 0) return fail(NRR_ERR_INVALID_ARG, "window must be >= 0 (got %d)", window);
+    if (!flt || !workspace) return fail(NRR_ERR_INVALID_ARG, "flt and workspace must be non-NULL");
+    const nrr::StatsLayout L = nrr::stats_layout(dtype, dims, block);
+    if (workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "workspace %zu < %zu bytes", workspace_bytes,
+                    L.total);
+    const nrr::MatchArgs a = match_args(nullptr, flt, dims, nullptr, 0, block, window, nullptr,
+                                        nullptr, nullptr, workspace, L);
+    const bool pairs = plan_reads_pairs(dtype, a);
+    note_pairs(workspace, pairs);
+    const int32_t b3[3] = {block, block, block};
+    return hip_status(nrr::launch_stats(flt, dtype, dims, b3, pairs, workspace,
                                         static_cast<hipStream_t>(stream)),
                       "window statistics launch");
 }
@@ -412,7 +473,13 @@ nrr_status nrr_block_match(const void *ref, const void *flt, nrr_dtype dtype,
                                workspace, workspace_bytes, &L);
     if (s != NRR_OK || n == 0) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipError_t e = nrr::launch_stats(flt, dtype, dims, block, workspace, st);
+    // the plane-pair volume only when the planned search reads it
+    const nrr::MatchArgs a =
+        match_args(ref, flt, dims, centers, n, block, window, disp, ncc, conf, workspace, L);
+    const bool pairs = plan_reads_pairs(dtype, a);
+    note_pairs(workspace, pairs);
+    const int32_t b3[3] = {block, block, block};
+    hipError_t e = nrr::launch_stats(flt, dtype, dims, b3, pairs, workspace, st);
     if (e != hipSuccess) return hip_status(e, "window statistics launch");
     return run_match(ref, flt, dtype, dims, centers, n, block, window, disp, ncc, conf, workspace,
                      L, st);
@@ -442,6 +509,7 @@ nrr_status nrr_block_match_surface(const void *ref, const void *flt, nrr_dtype d
     const int64_t side = 2 * (int64_t)window + 1;
     hipError_t e = nrr::launch_fill(surface, n * side * side * side, NAN, st);
     if (e != hipSuccess) return hip_status(e, "surface fill");
+    note_pairs(workspace, true);
     if ((e = nrr::launch_stats(flt, dtype, dims, block, workspace, st)) != hipSuccess)
         return hip_status(e, "window statistics launch");
     e = nrr::launch_match_surface(dtype, arith, a, surface, st);

@@ -111,6 +111,9 @@ struct StatsLayout {
 };
 StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
 
+// The plane-pair volume of a 12-bit volume alone (what the dot2 search reads).
+hipError_t launch_pair_volume(const uint16_t *flt, const int32_t dims[3], uint32_t *pairs,
+                              hipStream_t stream);
 hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3], int32_t block,
                         void *workspace, hipStream_t stream);
 // Per-axis block (bx, by, bz); `pairs`: also the plane-pair volume (12-bit).

@@ -27,60 +27,39 @@ struct SelectState {
     int64_t take_eq;  // how many candidates with key == kth are kept (lowest indices)
 };
 
-// Wavefronts walk the candidates; a wavefront reads one block with its lanes
-// packed along the block's rows (element e = lane + 64 k in x, y, z order),
-// so a load instruction touches a few consecutive rows rather than 64 of
-// them, sums exactly in integers and reduces across the wavefront.  A lane's
-// element offsets advance by a fixed step with carries (no division per
-// element).  Workgroups are dealt to the 8 XCDs in turn; each XCD takes a
-// contiguous eighth of the candidates and its wavefronts walk it together,
-// so the blocks in flight on an XCD overlap in its L2.
+// One wavefront per candidate block (grids whose candidates do not overlap,
+// or whose tile region is too large for the tiled kernel): lanes take the
+// block's by*bz rows, sum them exactly in integers and reduce across the
+// wavefront.
 __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restrict__ vol, int nx,
                                                         int ny, BoxGrid G, int64_t n,
                                                         uint64_t *__restrict__ keys) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
+    if (g >= n) return;  // whole wavefront leaves together
     const int bx = G.b[0], by = G.b[1], bz = G.b[2];
-    const int nb = bx * by * bz;
-    const int64_t plane = (int64_t)ny * nx;
-    // the lane's first element and the step of 64 elements
-    const int r0 = lane / bx, x0l = lane - r0 * bx;
-    const int y0l = r0 % by, z0l = r0 / by;
-    const int sx = 64 % bx, sr = 64 / bx;
-    // this workgroup's XCD (dispatch order) and its wavefront among the XCD's
-    const int xcd = blockIdx.x & 7, nx_wg = (int)(gridDim.x >> 3);  // grid: multiple of 8
-    const int64_t waves = (int64_t)nx_wg * 4;
-    const int64_t per = (n + 7) / 8, lo = xcd * per, hi = min(n, lo + per);
-    for (int64_t g = lo + (int64_t)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); g < hi; g += waves) {
-        // candidate coordinates in 32-bit arithmetic (grids hold < 2^31 candidates)
-        const int gi = (int)g, gxy = G.g[0] * G.g[1];
-        const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
-        const uint16_t *base =
-            vol + ((int64_t)iz * G.s[2] * ny + (int64_t)iy * G.s[1]) * nx + (int64_t)ix * G.s[0];
-        int x = x0l, y = y0l, z = z0l;
-        uint64_t s = 0, q = 0;
-        // chunks of 16 elements per lane: all 16 loads are in flight before
-        // the first is summed
-        for (int e = lane; e < nb; e += 64) {
-            const uint32_t v = base[(int64_t)z * plane + (int64_t)y * nx + x];
-            s += v;
-            q += v * v;
-            x += sx;
-            y += sr;
-            if (x >= bx) {
-                x -= bx;
-                ++y;
-            }
-            while (y >= by) {
-                y -= by;
-                ++z;
-            }
+    // candidate coordinates in 32-bit arithmetic (grids hold < 2^31 candidates)
+    const int gi = (int)g, gxy = G.g[0] * G.g[1];
+    const int iz = gi / gxy, rr = gi - iz * gxy, iy = rr / G.g[0], ix = rr - iy * G.g[0];
+    const int64_t x0 = (int64_t)ix * G.s[0], y0 = (int64_t)iy * G.s[1], z0 = (int64_t)iz * G.s[2];
+    uint64_t s = 0, q = 0;
+    for (int r = lane; r < by * bz; r += 64) {
+        const int z = r / by, y = r - z * by;
+        const uint16_t *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
+        uint64_t rs = 0, rq = 0;
+        for (int x = 0; x < bx; ++x) {
+            const uint64_t v = row[x];
+            rs += v;
+            rq += v * v;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            s += __shfl_xor(s, off);
-            q += __shfl_xor(q, off);
-        }
-        if (lane == 0) keys[g] = (uint64_t)nb * q - s * s;  // >= 0 by Cauchy-Schwarz
+        s += rs;
+        q += rq;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        q += __shfl_xor(q, off);
+    }
+    if (lane == 0) keys[g] = (uint64_t)bx * by * bz * q - s * s;  // >= 0 by Cauchy-Schwarz
 }
 
 // Tiled keys for overlapping candidates (tile regions up to 120 voxels a side): a
@@ -202,10 +181,13 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
 // the most significant byte; one workgroup.
 // K comes from `k`, or from *kd when kd is given (a count made on the device);
 // K = 0 selects nothing.
+// With `tiles`, it also writes the per-tile counts of keys > K-th and == K-th
+// that the compaction reads (one wavefront per tile of kSelectTile).
 __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
                                                            int64_t n, int64_t k,
                                                            const int64_t *__restrict__ kd,
-                                                           SelectState *__restrict__ st) {
+                                                           SelectState *__restrict__ st,
+                                                           int64_t *__restrict__ tiles) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_need, s_bucket;
@@ -311,6 +293,27 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
         // bytes below `top`+8 were all resolved; bytes above are zero in every key
         st->kth = s_prefix;
         st->take_eq = s_need;
+    }
+    if (tiles) {
+        const uint64_t kth = s_prefix;
+        const int lane = tid & 63;
+        const int64_t ntiles = (n + kSelectTile - 1) / kSelectTile;
+        for (int64_t t = tid >> 6; t < ntiles; t += blockDim.x >> 6) {
+            int64_t gt = 0, eq = 0;
+            for (int64_t g = t * kSelectTile + lane; g < min(n, (t + 1) * kSelectTile); g += 64) {
+                const uint64_t kv = keys[g];
+                gt += kv > kth;
+                eq += kv == kth;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                gt += __shfl_xor(gt, off);
+                eq += __shfl_xor(eq, off);
+            }
+            if (lane == 0) {
+                tiles[2 * t] = gt;
+                tiles[2 * t + 1] = eq;
+            }
+        }
     }
 }
 
@@ -1137,11 +1140,9 @@ void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const 
                                 (unsigned)G.g[2]),
                            dim3(256), (size_t)rx * ry * 2 + (size_t)ry * KT * 8, stream,
                            static_cast<const uint16_t *>(vol), dims[0], dims[1], G, keys);
-    else if (dtype == NRR_U16)  // wavefronts walk the candidates: 8 workgroups per CU at most
-        hipLaunchKernelGGL(k_block_keys_u16,
-                           dim3((unsigned)(std::min<int64_t>((n + 31) / 32, 256) * 8)), dim3(256),
-                           0, stream, static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n,
-                           keys);
+    else if (dtype == NRR_U16)
+        hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
+                           static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n, keys);
     else
         hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            stream, static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
@@ -1197,11 +1198,12 @@ void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t
             hipLaunchKernelGGL(k_radix_pick, dim3(1), dim3(256), 0, stream, rows, kRadixRows,
                                shift, rs, st);
         }
-    } else {
-        hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st);
+        hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys,
+                           n, st, tiles);
+    } else {  // one workgroup: the K-th key, then the tile counts
+        hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st,
+                           tiles);
     }
-    hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
-                       st, tiles);
     hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
                        tiles, G, k, kd, centers);
 }

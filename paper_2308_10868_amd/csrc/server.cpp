@@ -249,7 +249,6 @@ hipError_t enqueue(nrr_server *S, Request &q) {
         } else {
             e = hipStreamWaitEvent(st, cs->ready, 0);  // made by an earlier request
         }
-        if (e == hipSuccess) e = nrr::launch_stats(flt, r.dtype, r.dims, r.block, b + f.stats, st);
         if (e != hipSuccess) return e;
         const nrr::StatsLayout L = nrr::stats_layout(r.dtype, r.dims, r.block);
         nrr::MatchArgs a;
@@ -269,6 +268,12 @@ hipError_t enqueue(nrr_server *S, Request &q) {
         a.disp = reinterpret_cast<int32_t *>(b + f.disp);
         a.ncc = reinterpret_cast<float *>(b + f.ncc);
         a.conf = reinterpret_cast<float *>(b + f.conf);
+        // window statistics, with the plane-pair volume only for the dot2 form
+        nrr::TileShape t;
+        const bool pairs = r.dtype == NRR_U16 && (!nrr::match_plan(r.dtype, a, &t) || t.arith == 0);
+        const int32_t b3[3] = {r.block, r.block, r.block};
+        if ((e = nrr::launch_stats(flt, r.dtype, r.dims, b3, pairs, b + f.stats, st)) != hipSuccess)
+            return e;
         if ((e = nrr::launch_match(r.dtype, a, st)) != hipSuccess) return e;
         const size_t k = (size_t)f.k;
         if (r.centers) e = hipMemcpyAsync(r.centers, centers, k * 12, hipMemcpyDefault, st);

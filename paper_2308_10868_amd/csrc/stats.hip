@@ -39,6 +39,16 @@ constexpr int PW = TX + MAXB - 1, PH = TY + MAXB - 1;
 constexpr int PATCH = PH * PW;
 constexpr int PER = (PATCH + 255) / 256;  // patch elements staged per thread
 
+// Workgroup barrier for LDS traffic only.  __syncthreads also orders global
+// memory, which on this architecture means waiting for every load in flight
+// (loads and stores share one counter), including the planes fetched ahead;
+// this kernel's global stores are read by no other thread of the launch.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Shared body of the two statistics kernels.  V: staged voxel type, A/AQ:
 // row and plane sums of F and F^2, AS/AQQ: block sums.  SLIDE: integer sums
 // (exact) slide along z; floating sums are re-added from the ring so no
@@ -70,26 +80,44 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
     const bool lastz = z0 + zc >= oz;  // the last run also owns the planes past its origins
     const int64_t pstride = (int64_t)ny * nx;
     const Src *pbase = flt + (int64_t)y0 * nx + x0;
-    auto fetch = [&](V (&reg)[PER], int zi) {
-        const Src *pl = pbase + (int64_t)zi * pstride;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) reg[k] = (gok[k] && zi < zend) ? conv(pl[goff[k]]) : V(0);
+    // Loads are issued unconditionally (elements outside the volume or past
+    // the run read the tile's first voxel of a plane inside the volume) and
+    // kept raw; the mask and the conversion are applied when the values go
+    // to LDS a plane later, so no wait follows a load in the step it is
+    // issued in.
+    struct Raw {
+        Src v[PER];
+        uint32_t ok;  // bit k: element k is inside the volume and the run
     };
-    V r1[PER], r2[PER];
+    auto fetch = [&](Raw &r, int zi) {
+        const Src *pl = pbase + (int64_t)min(zi, nz - 1) * pstride;
+        r.ok = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const bool ok = gok[k] && zi < zend;
+            r.ok |= (uint32_t)ok << k;
+            r.v[k] = pl[ok ? goff[k] : 0];
+        }
+    };
+    auto value = [&](const Raw &r, int k) { return ((r.ok >> k) & 1) ? conv(r.v[k]) : V(0); };
+    Raw r1, r2;
     fetch(r1, z0);
 #pragma unroll
-    for (int k = 0; k < PER; ++k) patch[tid + 256 * k] = r1[k];
+    for (int k = 0; k < PER; ++k) patch[tid + 256 * k] = value(r1, k);
     fetch(r1, z0 + 1);
-    __syncthreads();
+    lds_barrier();
     AS S = 0;
     AQQ QQ = 0;
     const int nseg = ph * (TX / SEG);
-    for (int zi = z0; zi < zend; ++zi) {
+    // one plane step; rn holds plane zi + 1 (fetched a step earlier), rf
+    // receives plane zi + 2.  The loop runs two steps per iteration with the
+    // buffers' roles swapped, so no register copy waits on a load in flight.
+    auto step = [&](int zi, Raw &rn, Raw &rf) {
         const int cur = (zi - z0) & 1;
         const V *pc = patch + cur * PATCH;
-        fetch(r2, zi + 2);
+        fetch(rf, zi + 2);
         if constexpr (std::is_same<V, int32_t>::value) {
-            // plane-pair words of this plane (r1 holds the next plane: the
+            // plane-pair words of this plane (rn holds the next plane: the
             // caller asks for them only when a block spans two planes or more,
             // so the next plane of an owned one is always fetched)
             if (pairs && (zi < z0 + zc || lastz)) {
@@ -97,7 +125,7 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
 #pragma unroll
                 for (int k = 0; k < PER; ++k)
                     if (pown[k]) {
-                        const int hi = zi + 1 < nz ? r1[k] : 0;
+                        const int hi = zi + 1 < nz ? value(rn, k) : 0;
                         pl[goff[k]] = (uint32_t)(uint16_t)pc[tid + 256 * k] |
                                       (uint32_t)(uint16_t)hi << 16;
                     }
@@ -125,7 +153,7 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
                 rq[r * TX + xs + u] = qv;
             }
         }
-        __syncthreads();
+        lds_barrier();
         A P = 0;  // then along y
         AQ Q = 0;
         for (int k = 0; k < by; ++k) {
@@ -158,11 +186,12 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
         }
         V *pn = patch + (cur ^ 1) * PATCH;
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            pn[tid + 256 * k] = r1[k];
-            r1[k] = r2[k];
-        }
-        __syncthreads();
+        for (int k = 0; k < PER; ++k) pn[tid + 256 * k] = value(rn, k);
+        lds_barrier();
+    };
+    for (int zi = z0; zi < zend; zi += 2) {
+        step(zi, r1, r2);
+        if (zi + 1 < zend) step(zi + 1, r2, r1);
     }
 }
 
@@ -377,6 +406,14 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
         hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
                            static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
                            L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_volume(const uint16_t *flt, const int32_t dims[3], uint32_t *pairs,
+                              hipStream_t stream) {
+    const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+    hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)((nvox + 1023) / 1024)), dim3(256), 0, stream,
+                       flt, nvox, (int64_t)dims[0] * dims[1], pairs);
     return hipGetLastError();
 }
 

@@ -122,3 +122,31 @@ def test_unknown_shape_is_rejected():
         nrr.set_tuned_shape(nrr.F32, 7, W, {"arith": 1, "rx": 6, "ry": 6, "nt": 256, "pf": 0})
     with pytest.raises(nrr.NrrError):  # the matrix-core form serves 12-bit data only
         nrr.set_tuned_shape(nrr.F32, 7, W, {"arith": 2, "rx": 0, "ry": 0, "nt": 256, "pf": -1})
+
+
+def test_statistics_for_a_window_then_another_plan(monkeypatch):
+    """nrr_window_stats_for writes the plane-pair volume only when the planned
+    search reads it (not for the matrix-core form); a prepared search whose
+    plan has changed since (here to dot2) adds it itself."""
+    import torch
+
+    p = synth.gen_mri_u16(seed=3, dims=(64, 64, 48))
+    b, w = 7, 5
+    ref, flt = to_dev(p.ref), to_dev(p.flt)
+    centers = nrr.select_blocks(ref, b, b, 0.3)
+    assert nrr.match_plan(nrr.U16, p.dims, b, w)["arith"] == 2
+    want = [to_host(t) for t in nrr.block_match(ref, flt, centers, b, w)]
+    ws = nrr.window_stats(flt, b, window=w)  # no pair volume
+    got = [to_host(t) for t in nrr.block_match(ref, flt, centers, b, w, workspace=ws,
+                                               prepared=True)]
+    for x, y in zip(want, got):
+        assert np.array_equal(x, y)
+    monkeypatch.setenv("NRR_ARITH", "dot2")
+    assert nrr.match_plan(nrr.U16, p.dims, b, w)["arith"] == 0
+    d, n, c = nrr.block_match(ref, flt, centers, b, w, workspace=ws, prepared=True)
+    torch.cuda.synchronize()
+    check_match(p.ref, p.flt, to_host(centers), b, w, to_host(d), to_host(n), to_host(c),
+                "dot2 after statistics made for the matrix-core form")
+    ws2 = nrr.window_stats(flt, b, window=w)  # planned for dot2: with the pair volume
+    d2, n2, c2 = nrr.block_match(ref, flt, centers, b, w, workspace=ws2, prepared=True)
+    assert np.array_equal(to_host(d2), to_host(d)) and np.array_equal(to_host(n2), to_host(n))
