@@ -332,10 +332,9 @@ __device__ inline void stage_rows_f32(const float *__restrict__ src, int nx, int
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (live[u]) {
-                V w;
+                // word writes: rows start at any word (odd plane stride)
 #pragma unroll
-                for (int e = 0; e < CW; ++e) w[e] = __float_as_uint(v[u][e] - c);
-                *reinterpret_cast<V *>(dst + off[u]) = w;
+                for (int e = 0; e < CW; ++e) dst[off[u] + e] = __float_as_uint(v[u][e] - c);
             }
     }
 }
@@ -530,10 +529,15 @@ __device__ __attribute__((always_inline)) inline void match_one(const Params &p,
     // ---- block statistics and the staged T table
     // Plane stride: lanes of a wavefront take consecutive dz, so the stride
     // spreads their reads over the LDS banks: odd (one pad dword) for the
-    // element-staged window, 4 x odd for chunk-staged windows (whole 16-byte
-    // chunks: 16 consecutive planes still hit distinct banks).
-    const int plane =
-        ROWS ? PY * pitch + (((PY * pitch / CW) & 1) ? 0 : CW) : PY * pitch + ZPAD;
+    // element-staged and the float windows, 4 x odd for the 12-bit
+    // chunk-staged windows (whole 16-byte chunks: 16 consecutive planes still
+    // hit distinct banks).
+    // (float windows: an odd plane stride in words, since their products
+    // read single words with consecutive lanes on consecutive dz planes; a
+    // stride of 4 x odd words put 64 lanes on 8 banks)
+    const int plane = ROWS ? (U16 ? PY * pitch + (((PY * pitch / CW) & 1) ? 0 : CW)
+                                  : PY * pitch + 1)
+                           : PY * pitch + ZPAD;
     auto stage_chunk = [&](int zc0, int ezc, float c) {
         if constexpr (ARITH == DOT2)  // plain copies of the precomputed pair words
             stage_rows<NT, 8>(p.pv, p.nx, p.ny, g.wx0, g.wy0, g.wz0 + zc0, ey, win, pitch,
@@ -969,7 +973,7 @@ size_t window_plane_bytes(const Variant &v, int w) {
     const int py = (d + v.ry - 1) / v.ry * v.ry + v.b - 1;
     if (v.arith == DOT2 || v.dtype == NRR_F32) {  // as the kernel's chunk-staged plane
         const int pl = (px + CW - 1) / CW * CW * py;
-        return (size_t)(pl + (((pl / CW) & 1) ? 0 : CW)) * 4;
+        return (size_t)(v.dtype == NRR_F32 ? pl + 1 : pl + (((pl / CW) & 1) ? 0 : CW)) * 4;
     }
     return ((size_t)px * py + ZPAD) * 4;
 }
