@@ -284,6 +284,16 @@ nrr_status nrr_block_match_aniso_prepared(const void *ref, const void *flt, nrr_
                                           float *conf, const void *workspace,
                                           size_t workspace_bytes, void *stream);
 
+/* Every kernel relies on the dtype's contract (12-bit data: values 0..4095,
+ * which the exact integer sums, the int16 offsets and the fp16 operands
+ * need; float data: finite values) and does not check it: data outside it
+ * give undefined results with NRR_OK.  nrr_check_volume counts, on
+ * `stream`, the voxels of vol (device, dims[2]*dims[1]*dims[0] of dtype)
+ * that break it into *bad_device (device int64), for callers that cannot
+ * vouch for their data.  INVALID_ARG for NULL pointers or dims < 1. */
+nrr_status nrr_check_volume(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            int64_t *bad_device, void *stream);
+
 /* Directional confidence for the biomechanical solve.  The FEM update
  * equation weights each block's displacement by a confidence matrix S; the
  * paper gives no formula for it.  This returns, per block centred at

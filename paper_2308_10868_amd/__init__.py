@@ -141,6 +141,7 @@ def load():
         "nrr_select_blocks_static": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P]),
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_window_stats_for": (st, [P, ctypes.c_int, P, I32, I32, P, SZ, P]),
+        "nrr_check_volume": (st, [P, ctypes.c_int, P, P, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
         "nrr_aniso_workspace_bytes": (st, [ctypes.c_int, P, P, P, P, P]),
@@ -332,6 +333,19 @@ def select_blocks_ex(vol, block: int, stride: int, fraction: float, mask=None,
                                     ctypes.c_void_p(kd.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                                     ws.numel(), _stream(vol)))
     return out[:int(kd.item())]
+
+
+def check_volume(vol) -> int:
+    """Number of voxels of a device volume outside its dtype's contract
+    (12-bit data above 4095, float data not finite); synchronises the
+    stream.  The other calls do not check: such data give undefined
+    results."""
+    torch = _torch()
+    dt, dims = _vol_info(vol)
+    bad = torch.zeros(1, dtype=torch.int64, device=vol.device)
+    _check(load().nrr_check_volume(ctypes.c_void_p(vol.data_ptr()), dt, _dims3(dims),
+                                   ctypes.c_void_p(bad.data_ptr()), _stream(vol)))
+    return int(bad.item())
 
 
 def window_stats(flt, block: int, workspace=None, window=None):

@@ -750,6 +750,20 @@ nrr_status nrr_block_match_aniso_prepared(const void *ref, const void *flt, nrr_
                      L, static_cast<hipStream_t>(stream));
 }
 
+nrr_status nrr_check_volume(const void *vol, nrr_dtype dtype, const int32_t dims[3],
+                            int64_t *bad_device, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    if (!dims || !vol || !bad_device)
+        return fail(NRR_ERR_INVALID_ARG, "vol, dims and bad_device must be non-NULL");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1) return fail(NRR_ERR_INVALID_ARG, "dims[%d] must be >= 1", a);
+    const int64_t n = (int64_t)dims[0] * dims[1] * dims[2];
+    return hip_status(nrr::launch_check_volume(vol, dtype, n, bad_device,
+                                               static_cast<hipStream_t>(stream)),
+                      "volume check launch");
+}
+
 nrr_status nrr_structure_confidence(const void *ref, nrr_dtype dtype, const int32_t dims[3],
                                     const int32_t *centers, int64_t n, int32_t block,
                                     const float *conf, float *out, void *stream) {

@@ -111,6 +111,9 @@ struct StatsLayout {
 };
 StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block);
 
+// Count of voxels outside the dtype's contract into the device int64 *bad.
+hipError_t launch_check_volume(const void *vol, nrr_dtype dtype, int64_t n, int64_t *bad,
+                               hipStream_t stream);
 // The plane-pair volume of a 12-bit volume alone (what the dot2 search reads).
 hipError_t launch_pair_volume(const uint16_t *flt, const int32_t dims[3], uint32_t *pairs,
                               hipStream_t stream);

@@ -27,6 +27,8 @@
 // workgroup.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <type_traits>
 
 #include "nrr_internal.h"
@@ -406,6 +408,46 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
         hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
                            static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
                            L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
+    return hipGetLastError();
+}
+
+// Voxels outside the dtype's contract (12-bit data above 4095, float data
+// not finite), counted into *bad.
+__global__ __launch_bounds__(256) void k_check_u16(const uint16_t *__restrict__ v, int64_t n,
+                                                   unsigned long long *__restrict__ bad) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        c += v[i] > 4095;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(bad, c);
+}
+
+__global__ __launch_bounds__(256) void k_check_f32(const float *__restrict__ v, int64_t n,
+                                                   unsigned long long *__restrict__ bad) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        c += !isfinite(v[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(bad, c);
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+hipError_t launch_check_volume(const void *vol, nrr_dtype dtype, int64_t n, int64_t *bad,
+                               hipStream_t stream) {
+    unsigned long long *b = reinterpret_cast<unsigned long long *>(bad);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, stream, b);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    if (n > 0) {
+        if (dtype == NRR_U16)
+            hipLaunchKernelGGL(k_check_u16, dim3(blocks), dim3(256), 0, stream,
+                               static_cast<const uint16_t *>(vol), n, b);
+        else
+            hipLaunchKernelGGL(k_check_f32, dim3(blocks), dim3(256), 0, stream,
+                               static_cast<const float *>(vol), n, b);
+    }
     return hipGetLastError();
 }
 

@@ -70,3 +70,20 @@ def test_statistics_table_and_pair_volume(dims, b, seed):
     hi = np.zeros_like(lo)
     hi[:-1] = lo[1:]
     assert np.array_equal(pairs, lo | hi << 16)
+
+
+def test_check_volume_counts_voxels_outside_the_contract():
+    """nrr_check_volume: 12-bit voxels above 4095 and non-finite floats."""
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nrr.load()
+    v = np.random.default_rng(0).integers(0, 4096, size=(9, 10, 11)).astype(np.uint16)
+    assert nrr.check_volume(to_dev(v)) == 0
+    v[3, 4, 5] = 4096
+    v[8, 9, 10] = 65535
+    assert nrr.check_volume(to_dev(v)) == 2
+    f = np.random.default_rng(1).standard_normal((5, 6, 7)).astype(np.float32)
+    assert nrr.check_volume(to_dev(f)) == 0
+    f[0, 0, 0], f[4, 5, 6], f[2, 2, 2] = np.nan, np.inf, -np.inf
+    assert nrr.check_volume(to_dev(f)) == 3
