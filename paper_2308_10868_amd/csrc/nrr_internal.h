@@ -26,7 +26,7 @@ struct SelectLayout {
     int64_t n_tiles;
 };
 // Grids of more candidates take the multi-workgroup radix select.
-constexpr int64_t kRadixMultiMin = 1 << 16;
+constexpr int64_t kRadixMultiMin = 1 << 15;
 // variants: room for the selection variants on large grids as well
 SelectLayout select_layout(int64_t n_candidates, bool variants = false);
 

@@ -177,12 +177,17 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
     }
 }
 
-// Radix select of the K-th largest key (1 <= K <= n), 8 bits per pass from
-// the most significant byte; one workgroup.
+// Radix select of the K-th largest key, 8 bits per pass from the most
+// significant byte; one 1024-thread workgroup for grids of at most
+// kRadixMultiMin candidates, whose keys it holds in registers (thread t
+// holds keys t + 1024 j), so the passes wait on no memory.
 // K comes from `k`, or from *kd when kd is given (a count made on the device);
 // K = 0 selects nothing.
 // With `tiles`, it also writes the per-tile counts of keys > K-th and == K-th
 // that the compaction reads (one wavefront per tile of kSelectTile).
+constexpr int kThrKeys = (int)(kRadixMultiMin / 1024);  // keys per thread
+static_assert(kRadixMultiMin % 1024 == 0, "whole keys per thread");
+
 __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
                                                            int64_t n, int64_t k,
                                                            const int64_t *__restrict__ kd,
@@ -190,57 +195,39 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
                                                            int64_t *__restrict__ tiles) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int64_t s_need, s_bucket;
+    __shared__ int64_t s_need;
     __shared__ uint64_t s_or;
-    // once the bucket holding the K-th key fits, its keys move to LDS and the
-    // remaining digit passes read them there instead of the whole key array
-    constexpr int CAP = 6144;
-    __shared__ uint64_t lk[CAP];
-    __shared__ int s_fill;
     const int tid = threadIdx.x;
     if (tid == 0) {
         s_prefix = 0;
         s_mask = 0;
         s_need = kd ? *kd : k;
         s_or = 0;
-        s_bucket = n;
-        s_fill = 0;
+    }
+    uint64_t kr[kThrKeys];  // all loads issued before any is used
+#pragma unroll
+    for (int j = 0; j < kThrKeys; ++j) {
+        const int64_t i = (int64_t)j * 1024 + tid;
+        kr[j] = i < n ? keys[i] : 0;
     }
     __syncthreads();
     // skip leading bytes that are zero in every key
     uint64_t orv = 0;
-    for (int64_t i = tid; i < n; i += 4 * blockDim.x) {
-        orv |= keys[i];
-        if (i + blockDim.x < n) orv |= keys[i + blockDim.x];
-        if (i + 2 * blockDim.x < n) orv |= keys[i + 2 * blockDim.x];
-        if (i + 3 * blockDim.x < n) orv |= keys[i + 3 * blockDim.x];
-    }
+#pragma unroll
+    for (int j = 0; j < kThrKeys; ++j) orv |= kr[j];
     for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off);
     if ((tid & 63) == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
     __syncthreads();
     int top = 56;
     while (top > 0 && ((s_or >> top) & 0xff) == 0) top -= 8;
-    bool local = false;  // keys read from lk (uniform)
-    int64_t cnt = n;
     for (int shift = top; shift >= 0; shift -= 8) {
         for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
         __syncthreads();
         const uint64_t prefix = s_prefix, mask = s_mask;
-        constexpr int UNR = 8;  // keys loaded per thread before any is counted
-        const int64_t iters = (cnt + blockDim.x - 1) / blockDim.x;
-        for (int64_t it = 0; it < iters; it += UNR) {  // uniform trip count: ballots converge
-            uint64_t kv[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int64_t i = (it + u) * blockDim.x + tid;
-                kv[u] = i < cnt ? (local ? lk[i] : keys[i]) : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-                const int64_t i = (it + u) * blockDim.x + tid;
-                const bool valid = i < cnt && (kv[u] & mask) == prefix;
-                hist_add(hist, (uint32_t)((kv[u] >> shift) & 0xff), valid);
-            }
+        for (int j = 0; j < kThrKeys; ++j) {  // uniform trip count: ballots converge
+            const bool valid = (int64_t)j * 1024 + tid < n && (kr[j] & mask) == prefix;
+            hist_add(hist, (uint32_t)((kr[j] >> shift) & 0xff), valid);
         }
         __syncthreads();
         if (tid < 64) {  // wavefront 0: find the digit holding the need-th largest key
@@ -269,7 +256,6 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
                         s_need = need - cum;
                         s_prefix = prefix | ((uint64_t)d << shift);
                         s_mask = mask | (0xffull << shift);
-                        s_bucket = h4[j];
                         break;
                     }
                     cum += h4[j];
@@ -277,17 +263,6 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
             }
         }
         __syncthreads();
-        if (!local && shift > 0 && s_bucket <= CAP) {
-            // copy the keys of the chosen bucket (in any order) into LDS
-            const uint64_t p2 = s_prefix, m2 = s_mask;
-            for (int64_t i = tid; i < n; i += blockDim.x) {
-                const uint64_t kv = keys[i];
-                if ((kv & m2) == p2) lk[atomicAdd(&s_fill, 1)] = kv;
-            }
-            __syncthreads();
-            local = true;
-            cnt = s_fill;  // == s_bucket
-        }
     }
     if (tid == 0) {
         // bytes below `top`+8 were all resolved; bytes above are zero in every key

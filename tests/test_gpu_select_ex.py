@@ -184,9 +184,10 @@ def test_aniso_variants_mri_slices(torch_dev, conn):
 
 @pytest.mark.parametrize("dtype", ["u16", "f32"])
 def test_plain_selection_large_grid_with_ties(torch_dev, dtype):
-    """Grids above 65,536 candidates take the multi-workgroup radix select:
-    half the volume is flat, so thousands of candidates share the key 0 and
-    the K-th key falls among them (ties to the lower grid index)."""
+    """Grids above 32,768 candidates take the multi-workgroup radix select,
+    smaller ones the one-workgroup select with its keys in registers: half
+    the volume is flat, so thousands of candidates share the key 0 and the
+    K-th key falls among them (ties to the lower grid index)."""
     import torch
 
     p = synth.gen_random(70, (120, 100, 90), dtype, smooth=1.0)
@@ -198,3 +199,9 @@ def test_plain_selection_large_grid_with_ties(torch_dev, dtype):
         got = nrr.select_blocks(to_dev(ref), b, s, f)
         torch.cuda.synchronize()
         assert np.array_equal(to_host(got), want), (dtype, b, s, f)
+    small = ref[:64, :64, :64].copy()  # b 3, stride 2: 29,791 candidates (one workgroup)
+    for f in (0.6, 0.999):
+        want, _ = oracle.select(small, 3, 2, f)
+        got = nrr.select_blocks(to_dev(small), 3, 2, f)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(got), want), (dtype, "29,791", f)
