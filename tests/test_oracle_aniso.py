@@ -133,3 +133,32 @@ def test_ncc_at_agrees_with_the_search():
                 assert np.all(v[ok] <= n[ok])
     far = oracle.ncc_aniso_at(p.ref, p.flt, cen, np.tile([0, 0, 9], (3, 1)), b)
     assert np.all(np.isnan(far))
+
+
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_ncc_aniso_at_is_the_correlation_of_the_two_blocks(dtype):
+    """oracle.ncc_aniso_at against numpy.corrcoef of the two blocks sliced
+    out directly (ref block at c - h, flt block displaced by d), NaN where a
+    block leaves the volume, on an anisotropic block."""
+    p = synth.gen_random(41, (21, 17, 13), dtype, smooth=1.0)
+    b = np.array([5, 3, 7])  # x, y, z
+    h = (b - 1) // 2
+    dims = np.array(p.dims)
+    rng = np.random.default_rng(5)
+    centers = np.stack([rng.integers(0, dims[a], 120) for a in range(3)], axis=1).astype(np.int32)
+    disp = rng.integers(-4, 5, size=(120, 3)).astype(np.int32)
+    got = oracle.ncc_aniso_at(p.ref, p.flt, centers, disp, tuple(b))
+    inside = 0
+    for k in range(120):
+        lo_r = centers[k] - h
+        lo_f = lo_r + disp[k]
+        if np.any(lo_r < 0) or np.any(lo_r + b > dims) or np.any(lo_f < 0) or \
+                np.any(lo_f + b > dims):
+            assert np.isnan(got[k]), k
+            continue
+        inside += 1
+        t = p.ref[lo_r[2]:lo_r[2] + b[2], lo_r[1]:lo_r[1] + b[1], lo_r[0]:lo_r[0] + b[0]]
+        f = p.flt[lo_f[2]:lo_f[2] + b[2], lo_f[1]:lo_f[1] + b[1], lo_f[0]:lo_f[0] + b[0]]
+        want = np.corrcoef(t.astype(np.float64).ravel(), f.astype(np.float64).ravel())[0, 1]
+        assert abs(got[k] - want) <= 1e-12, (k, got[k], want)
+    assert inside >= 20

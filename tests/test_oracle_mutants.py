@@ -69,6 +69,10 @@ MUTANTS_ANISO = {
     "aniso_rows_along_y_too_short": (
         "for (int64_t y = 0; y < b[1]; ++y)\n            for (int64_t x = 0; x < b[0]; ++x) {\n                st +=",
         "for (int64_t y = 0; y < b[0]; ++y)\n            for (int64_t x = 0; x < b[0]; ++x) {\n                st +="),
+    "aniso_at_displacement_sign": ("lo_f[a] = lo_r[a] + disp[3 * k + a];",
+                                   "lo_f[a] = lo_r[a] - disp[3 * k + a];"),
+    "aniso_at_x_half_everywhere": ("            const int64_t h = (b[a] - 1) / 2;\n            lo_r[a] = centers[3 * k + a] - h;",
+                                   "            const int64_t h = (b[0] - 1) / 2;\n            lo_r[a] = centers[3 * k + a] - h;"),
     "aniso_tie_takes_last": (
         "if (v > best) {\n                        best = v;\n                        bd[0]",
         "if (v >= best) {\n                        best = v;\n                        bd[0]"),
