@@ -87,3 +87,38 @@ def test_check_volume_counts_voxels_outside_the_contract():
     assert nrr.check_volume(to_dev(f)) == 0
     f[0, 0, 0], f[4, 5, 6], f[2, 2, 2] = np.nan, np.inf, -np.inf
     assert nrr.check_volume(to_dev(f)) == 3
+
+
+def test_float_flatness_rule_near_its_limit():
+    """Float windows count as flat when N sum F^2 - (sum F)^2 <= 1e-12 N sum F^2
+    (FP64 box sums cannot resolve a smaller relative spread): their record
+    holds r = 0.  A level of 1000 with a spread rising from 1e-5 to 10 along
+    x puts windows on both sides of the limit; away from it (a factor of 4
+    either way) r must be 0 exactly on the flat side and 1/sqrt of the spread
+    (to 1e-6) on the other.  Record: {f64 sum F, f64 r} per block origin."""
+    import torch
+    from numpy.lib.stride_tricks import sliding_window_view
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    nx, ny, nz, b = 64, 9, 10, 3
+    rng = np.random.default_rng(9)
+    amp = 10.0 ** (-5.0 + 6.0 * np.arange(nx) / (nx - 1))  # 1e-5 .. 10
+    flt = (1000.0 + amp[None, None, :] * rng.standard_normal((nz, ny, nx))).astype(np.float32)
+    ws = nrr.window_stats(to_dev(flt), b)
+    torch.cuda.synchronize()
+    ox, oy, oz = nx - b + 1, ny - b + 1, nz - b + 1
+    rec = ws.cpu().numpy()[:ox * oy * oz * 16].view(np.float64).reshape(oz, oy, ox, 2)
+    w = sliding_window_view(flt.astype(np.float64), (b, b, b)).reshape(oz, oy, ox, -1)
+    n = b ** 3
+    s = w.sum(axis=-1)
+    q = (w * w).sum(axis=-1)
+    c = w - w.mean(axis=-1, keepdims=True)
+    spread = n * (c * c).sum(axis=-1)  # N sum (F - mean)^2 = N q - s^2, without cancellation
+    limit = 1e-12 * n * q
+    assert np.allclose(rec[..., 0], s, rtol=1e-12)
+    flat, live = spread < limit / 4, spread > 4 * limit
+    assert flat.sum() > 100 and live.sum() > 100
+    assert np.all(rec[..., 1][flat] == 0.0)
+    sure = spread > 1e5 * limit  # cancellation in N q - s^2 well below 1e-6 here
+    assert np.all(rec[..., 1][live] > 0.0)
+    assert np.allclose(rec[..., 1][sure], 1.0 / np.sqrt(spread[sure]), rtol=1e-6, atol=0)
