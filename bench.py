@@ -69,6 +69,9 @@ TRAFFIC_FILES = {
     ("mri_256x256x124_u16", "mfma"): ("k_match_mfma_mri_256x256x124_traffic.json",
                                       ["paper_2308_10868_amd/csrc/match_mfma.hip",
                                        "paper_2308_10868_amd/csrc/nrr_internal.h"]),
+    ("blobs_512x512x256_u16", "mfma"): ("k_match_mfma_blobs_512x512x256_traffic.json",
+                                        ["paper_2308_10868_amd/csrc/match_mfma.hip",
+                                         "paper_2308_10868_amd/csrc/nrr_internal.h"]),
     ("mri_aniso_256x256x124_u16", "fma"): ("k_match_aniso_u16_mri_256x256x124_traffic.json",
                                            ["paper_2308_10868_amd/csrc/match_aniso.hip",
                                             "paper_2308_10868_amd/csrc/nrr_internal.h"]),
