@@ -62,6 +62,58 @@ __global__ __launch_bounds__(256) void k_block_keys_u16(const uint16_t *__restri
     if (lane == 0) keys[g] = (uint64_t)bx * by * bz * q - s * s;  // >= 0 by Cauchy-Schwarz
 }
 
+// Keys by candidate rows (grids whose candidates do not overlap in x and y):
+// a workgroup takes the candidates of one (y, z) grid row whose columns fit
+// in 64 voxels.  Lane t owns voxel column x0 + t; the four wavefronts split
+// the block's bz planes (every load a contiguous run of 64 voxels, a plane's
+// by rows issued together) and each candidate adds its bx columns of the
+// four partial sums from LDS.
+__global__ __launch_bounds__(256) void k_block_keys_u16_rows(const uint16_t *__restrict__ vol,
+                                                             int nx, int ny, BoxGrid G, int cx,
+                                                             uint64_t *__restrict__ keys) {
+    __shared__ uint32_t col_s[4][64];
+    __shared__ uint64_t col_q[4][64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int bx = G.b[0], by = G.b[1], bz = G.b[2], sx = G.s[0];
+    const int c0 = blockIdx.x * cx, iy = blockIdx.y, iz = blockIdx.z;
+    const int ncx = min(cx, G.g[0] - c0);
+    const int width = (ncx - 1) * sx + bx;  // <= 64 by the choice of cx
+    const int64_t x0 = (int64_t)c0 * sx;
+    uint32_t a = 0;  // <= 225 voxels of 16 bits
+    uint64_t q = 0;
+    // columns in the gaps between candidates (stride above the edge) are skipped
+    if (lane < width && lane % sx < bx) {
+        const int64_t plane = (int64_t)ny * nx;
+        const uint16_t *base =
+            vol + ((int64_t)iz * G.s[2] * ny + (int64_t)iy * G.s[1]) * nx + x0 + lane;
+        for (int z = w; z < bz; z += 4) {
+            const uint16_t *p = base + z * plane;
+            uint32_t v[15];  // block edges are at most 15
+#pragma unroll
+            for (int y = 0; y < 15; ++y) v[y] = y < by ? p[(int64_t)y * nx] : 0u;
+#pragma unroll
+            for (int y = 0; y < 15; ++y) {
+                a += v[y];
+                q += (uint64_t)(v[y] * v[y]);  // a square of 16 bits fits 32
+            }
+        }
+    }
+    col_s[w][lane] = a;
+    col_q[w][lane] = q;
+    __syncthreads();
+    if (tid < ncx) {
+        uint64_t s = 0, qq = 0;
+        for (int k = 0; k < bx; ++k)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                s += col_s[j][tid * sx + k];
+                qq += col_q[j][tid * sx + k];
+            }
+        const int64_t g = ((int64_t)iz * G.g[1] + iy) * G.g[0] + c0 + tid;
+        keys[g] = (uint64_t)bx * by * bz * qq - s * s;
+    }
+}
+
 // Tiled keys for overlapping candidates (tile regions up to 120 voxels a side): a
 // workgroup takes 16 x 16 candidates in x and y at one candidate plane z.
 // For each of the block's bz voxel planes it stages the tile's region
@@ -178,31 +230,46 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
 }
 
 // Radix select of the K-th largest key, 8 bits per pass from the most
-// significant byte; one 1024-thread workgroup for grids of at most
-// kRadixMultiMin candidates, whose keys it holds in registers (thread t
-// holds keys t + 1024 j), so the passes wait on no memory.
+// significant set bit down; one 1024-thread workgroup for grids of at most
+// kRadixMultiMin candidates, whose keys it holds in registers (thread t holds
+// keys t + 1024 j), so the passes wait on no memory.  A pass counts digits
+// into 16 copies of the histogram (copy = lane mod 16: variance keys crowd a
+// few bins, and lanes adding to one LDS word serialise), folds them and picks
+// the digit that holds the need-th largest key.  Once at most 1024 keys match
+// the prefix found so far they are moved to an LDS list, one per thread, and
+// the remaining passes read only that.  The first pass is aligned to the
+// highest set bit of all keys; the last one may overlap bits already fixed
+// (those are equal in every key it counts, so the pick is unchanged).
 // K comes from `k`, or from *kd when kd is given (a count made on the device);
 // K = 0 selects nothing.
-// With `tiles`, it also writes the per-tile counts of keys > K-th and == K-th
-// that the compaction reads (one wavefront per tile of kSelectTile).
+// The same workgroup then writes the chosen blocks' centres in ascending grid
+// index (the ordered compaction, from the registers): per key slot and
+// wavefront it counts the keys above and equal to the K-th by ballots, scans
+// those counts in index order, and places each kept key by its rank.
 constexpr int kThrKeys = (int)(kRadixMultiMin / 1024);  // keys per thread
 static_assert(kRadixMultiMin % 1024 == 0, "whole keys per thread");
+constexpr int kThrCopies = 16;  // histogram copies (lane mod 16)
 
 __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
                                                            int64_t n, int64_t k,
                                                            const int64_t *__restrict__ kd,
-                                                           SelectState *__restrict__ st,
-                                                           int64_t *__restrict__ tiles) {
+                                                           SelectState *__restrict__ st, BoxGrid G,
+                                                           int32_t *__restrict__ centers) {
+    __shared__ __align__(16) uint32_t hist_c[256 * kThrCopies];  // [digit][copy]
     __shared__ uint32_t hist[256];
+    __shared__ uint64_t list[1024];
     __shared__ uint64_t s_prefix, s_mask;
     __shared__ int64_t s_need;
     __shared__ uint64_t s_or;
-    const int tid = threadIdx.x;
+    __shared__ uint32_t s_left, s_count;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t kk = kd ? *kd : k;  // K
     if (tid == 0) {
         s_prefix = 0;
         s_mask = 0;
-        s_need = kd ? *kd : k;
+        s_need = kk;
         s_or = 0;
+        s_count = 0;
     }
     uint64_t kr[kThrKeys];  // all loads issued before any is used
 #pragma unroll
@@ -211,26 +278,45 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
         kr[j] = i < n ? keys[i] : 0;
     }
     __syncthreads();
-    // skip leading bytes that are zero in every key
     uint64_t orv = 0;
 #pragma unroll
     for (int j = 0; j < kThrKeys; ++j) orv |= kr[j];
     for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off);
-    if ((tid & 63) == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
+    if (lane == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
     __syncthreads();
-    int top = 56;
-    while (top > 0 && ((s_or >> top) & 0xff) == 0) top -= 8;
-    for (int shift = top; shift >= 0; shift -= 8) {
-        for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
+    const int bits = s_or ? 64 - __clzll((long long)s_or) : 1;
+    bool in_list = false;  // workgroup-uniform
+    uint32_t n_list = 0;
+    for (int shift = bits > 8 ? bits - 8 : 0;; shift = shift > 8 ? shift - 8 : 0) {
         const uint64_t prefix = s_prefix, mask = s_mask;
+        if (!in_list) {
+            uint32_t *hrow = hist_c + (tid & (kThrCopies - 1));
+            for (int i = tid; i < 256 * kThrCopies; i += 1024) hist_c[i] = 0;
+            __syncthreads();
 #pragma unroll
-        for (int j = 0; j < kThrKeys; ++j) {  // uniform trip count: ballots converge
-            const bool valid = (int64_t)j * 1024 + tid < n && (kr[j] & mask) == prefix;
-            hist_add(hist, (uint32_t)((kr[j] >> shift) & 0xff), valid);
+            for (int j = 0; j < kThrKeys; ++j)
+                if ((int64_t)j * 1024 + tid < n && (kr[j] & mask) == prefix)
+                    atomicAdd(&hrow[((kr[j] >> shift) & 0xff) * kThrCopies], 1u);
+            __syncthreads();
+            if (tid < 256) {
+                const uint4 *c = reinterpret_cast<const uint4 *>(hist_c + tid * kThrCopies);
+                uint32_t t = 0;
+#pragma unroll
+                for (int q = 0; q < kThrCopies / 4; ++q) t += c[q].x + c[q].y + c[q].z + c[q].w;
+                hist[tid] = t;
+            }
+        } else {  // at most 1024 keys: one histogram
+            if (tid < 256) hist[tid] = 0;
+            __syncthreads();
+            if (tid < (int)n_list && (list[tid] & mask) == prefix)
+                atomicAdd(&hist[(list[tid] >> shift) & 0xff], 1u);
         }
         __syncthreads();
         if (tid < 64) {  // wavefront 0: find the digit holding the need-th largest key
+            // (every thread read the previous pass's s_left before this
+            // pass's first barrier; the picking lane's store comes later in
+            // this wavefront's program order than this one)
+            if (tid == 0) s_left = 0xffffffffu;
             // lane l owns bins 255-4l .. 252-4l (descending)
             uint32_t h4[4];
             uint32_t mine = 0;
@@ -256,6 +342,7 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
                         s_need = need - cum;
                         s_prefix = prefix | ((uint64_t)d << shift);
                         s_mask = mask | (0xffull << shift);
+                        s_left = h4[j];  // keys matching the new prefix
                         break;
                     }
                     cum += h4[j];
@@ -263,31 +350,105 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
             }
         }
         __syncthreads();
+        if (shift == 0) break;
+        if (!in_list && s_need > 0 && s_left <= 1024) {
+            // move the keys that still match to the LDS list: one slot
+            // range per wavefront (one atomic), then its keys in slot order
+            const uint64_t p2 = s_prefix, m2 = s_mask;
+            uint32_t mm = 0, wave_total = 0;
+#pragma unroll
+            for (int j = 0; j < kThrKeys; ++j) {
+                const bool m = (int64_t)j * 1024 + tid < n && (kr[j] & m2) == p2;
+                mm |= (uint32_t)m << j;
+                wave_total += (uint32_t)__popcll(__ballot(m));
+            }
+            uint32_t base = 0;
+            if (lane == 0 && wave_total) base = atomicAdd(&s_count, wave_total);
+            base = __shfl(base, 0);
+#pragma unroll
+            for (int j = 0; j < kThrKeys; ++j) {
+                const bool m = (mm >> j) & 1;
+                const uint64_t b = __ballot(m);
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+                if (m && base + below < 1024) list[base + below] = kr[j];
+                base += (uint32_t)__popcll(b);
+            }
+            __syncthreads();
+            in_list = true;
+            n_list = min(s_count, 1024u);
+        }
     }
     if (tid == 0) {
-        // bytes below `top`+8 were all resolved; bytes above are zero in every key
         st->kth = s_prefix;
         st->take_eq = s_need;
     }
-    if (tiles) {
-        const uint64_t kth = s_prefix;
-        const int lane = tid & 63;
-        const int64_t ntiles = (n + kSelectTile - 1) / kSelectTile;
-        for (int64_t t = tid >> 6; t < ntiles; t += blockDim.x >> 6) {
-            int64_t gt = 0, eq = 0;
-            for (int64_t g = t * kSelectTile + lane; g < min(n, (t + 1) * kSelectTile); g += 64) {
-                const uint64_t kv = keys[g];
-                gt += kv > kth;
-                eq += kv == kth;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                gt += __shfl_xor(gt, off);
-                eq += __shfl_xor(eq, off);
-            }
-            if (lane == 0) {
-                tiles[2 * t] = gt;
-                tiles[2 * t + 1] = eq;
-            }
+    // ordered compaction: key 1024 j + tid sits in slot j of wavefront w's
+    // lane; index order is (slot, wavefront, lane)
+    __shared__ uint32_t pre[kThrKeys * 16];  // (above | equal << 16) per (slot, wavefront)
+    const uint64_t kth = s_prefix;
+    const int64_t take = s_need;  // equal keys kept, lowest indices first
+    uint32_t fgt = 0, feq = 0;  // bit j: key j of this thread is above / equal to the K-th
+#pragma unroll
+    for (int j = 0; j < kThrKeys; ++j) {
+        const bool in = (int64_t)j * 1024 + tid < n;
+        const bool gt = in && kr[j] > kth, eq = in && kr[j] == kth;
+        fgt |= (uint32_t)gt << j;
+        feq |= (uint32_t)eq << j;
+        const uint32_t a = (uint32_t)__popcll(__ballot(gt));
+        const uint32_t e = (uint32_t)__popcll(__ballot(eq));
+        if (lane == 0) pre[j * 16 + w] = a | e << 16;  // each < 2^16 (n <= 2^15)
+    }
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the 16 kThrKeys entries, 8 per lane
+        constexpr int PL = kThrKeys * 16 / 64;
+        uint32_t v[PL], sum = 0;
+#pragma unroll
+        for (int i = 0; i < PL; ++i) {
+            v[i] = pre[tid * PL + i];
+            sum += v[i];
+        }
+        uint32_t incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(incl, off);
+            if (tid >= off) incl += o;
+        }
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < PL; ++i) {
+            pre[tid * PL + i] = run;
+            run += v[i];
+        }
+    }
+    __syncthreads();
+    // counts, ranks and grid indices below 2^15 + 1: 32-bit arithmetic, and
+    // the grid coordinates by a float reciprocal corrected by one step
+    const int gxy = G.g[0] * G.g[1], take32 = (int)take, k32 = (int)kk;
+    const float inv_gxy = 1.0f / (float)gxy, inv_gx = 1.0f / (float)G.g[0];
+    auto div_small = [](int a, int d, float inv) {  // floor(a / d), 0 <= a < 2^24
+        int q = (int)((float)a * inv);
+        const int r = a - q * d;
+        return r < 0 ? q - 1 : (r >= d ? q + 1 : q);
+    };
+    const int nslots = (int)((n + 1023) / 1024);
+#pragma unroll 1
+    for (int j = 0; j < nslots; ++j) {  // the flags are bits: no key register is indexed
+        const int g = j * 1024 + tid;
+        const bool gt = (fgt >> j) & 1, eq = (feq >> j) & 1;
+        const uint64_t bg = __ballot(gt), be = __ballot(eq);
+        const uint32_t p = pre[j * 16 + w];
+        const int gt_before = (int)((p & 0xffff) + __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(bg >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bg, 0u)));
+        const int eq_before = (int)((p >> 16) + __builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(be >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)be, 0u)));
+        const bool keep = gt || (eq && eq_before < take32);
+        const int pos = gt_before + min(eq_before, take32);
+        if (keep && pos < k32) {
+            const int iz = div_small(g, gxy, inv_gxy), rr = g - iz * gxy;
+            const int iy = div_small(rr, G.g[0], inv_gx), ix = rr - iy * G.g[0];
+            centers[3 * pos + 0] = (int32_t)(ix * G.s[0] + (G.b[0] - 1) / 2);
+            centers[3 * pos + 1] = (int32_t)(iy * G.s[1] + (G.b[1] - 1) / 2);
+            centers[3 * pos + 2] = (int32_t)(iz * G.s[2] + (G.b[2] - 1) / 2);
         }
     }
 }
@@ -758,6 +919,20 @@ ExDirs ex_dirs(int connectivity) {
     return d;
 }
 
+// Adds the workgroup's total of `c` to *dst with one atomic (the per-wavefront
+// atomics on one address serialise at L2 across thousands of wavefronts).
+// Every thread of the 256-thread workgroup calls it.
+__device__ inline void wg_count_add(unsigned long long c, int64_t *dst) {
+    __shared__ unsigned long long part[4];
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t) atomicAdd((unsigned long long *)dst, t);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_ex_zero(int64_t *__restrict__ ctr) {
     if (threadIdx.x < 8) ctr[threadIdx.x] = 0;
 }
@@ -770,13 +945,12 @@ __global__ __launch_bounds__(256) void k_ex_init(const uint64_t *__restrict__ ke
                                                  uint32_t *__restrict__ above,
                                                  int64_t *__restrict__ ctr) {
     const int64_t n = (int64_t)G.g[0] * G.g[1] * G.g[2];
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool in = false;
-    if (g < n) {
+    unsigned long long n_in = 0;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256) {
         const int64_t gxy = (int64_t)G.g[0] * G.g[1];
         const int iz = (int)(g / gxy), r = (int)(g - iz * gxy), iy = r / G.g[0],
                   ix = r - iy * G.g[0];
-        in = true;
+        bool in = true;
         if (mask)
             in = mask[((int64_t)(iz * G.s[2] + (G.b[2] - 1) / 2) * ny +
                        (iy * G.s[1] + (G.b[1] - 1) / 2)) * nx +
@@ -791,15 +965,14 @@ __global__ __launch_bounds__(256) void k_ex_init(const uint64_t *__restrict__ ke
         }
         state[g] = in ? 0 : 3;
         above[g] = bits;
+        n_in += in;
     }
-    const uint64_t b = __ballot(in);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&ctr[EX_N_IN],
-                                                 (unsigned long long)__popcll(b));
+    wg_count_add(n_in, &ctr[EX_N_IN]);
 }
 
-// One round launch (see above); open candidates left after it are counted
-// into ctr[EX_OPEN + parity], and the other parity's counter is cleared for
-// the next launch.
+// One round launch (see above); a workgroup with open candidates left after
+// it sets ctr[EX_OPEN + parity] to 1 (the host only asks whether any are
+// left), and the other parity's flag is cleared for the next launch.
 __global__ __launch_bounds__(256) void k_ex_round(BoxGrid G, ExDirs D,
                                                   uint8_t *__restrict__ state,
                                                   const uint32_t *__restrict__ above, int parity,
@@ -861,16 +1034,14 @@ __global__ __launch_bounds__(256) void k_ex_round(BoxGrid G, ExDirs D,
         if (!s_changed) break;
         __syncthreads();
     }
-    int open = 0;
+    bool open = false;
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int e = tid + 256 * p;
         if (live[p]) state[gi[p]] = ts[e];
-        open += live[p] && ts[e] == 0;
+        open |= live[p] && ts[e] == 0;
     }
-    for (int off = 32; off > 0; off >>= 1) open += __shfl_xor(open, off);
-    if ((tid & 63) == 0 && open) atomicAdd((unsigned long long *)&ctr[EX_OPEN + parity],
-                                           (unsigned long long)open);
+    if (__syncthreads_or(open) && tid == 0) ctr[EX_OPEN + parity] = 1;
 }
 
 // Keys remapped for the final select (taken: key + 1, other: 0) and the taken
@@ -878,12 +1049,13 @@ __global__ __launch_bounds__(256) void k_ex_round(BoxGrid G, ExDirs D,
 __global__ __launch_bounds__(256) void k_ex_count(uint64_t *__restrict__ keys, int64_t n,
                                                   const uint8_t *__restrict__ state,
                                                   int64_t *__restrict__ ctr) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool taken = g < n && state[g] == 1;
-    if (g < n) keys[g] = taken ? keys[g] + 1 : 0;
-    const uint64_t b = __ballot(taken);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&ctr[EX_TAKEN],
-                                                 (unsigned long long)__popcll(b));
+    unsigned long long taken = 0;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256) {
+        const bool t = state[g] == 1;
+        keys[g] = t ? keys[g] + 1 : 0;
+        taken += t;
+    }
+    wg_count_add(taken, &ctr[EX_TAKEN]);
 }
 
 // K from the count rule over the candidates inside the mask, then the number
@@ -1081,7 +1253,8 @@ hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_
     const ExDirs D = ex_dirs(connectivity);
     launch_keys(vol, dtype, dims, G, n, keys, stream);
     hipLaunchKernelGGL(k_ex_zero, dim3(1), dim3(256), 0, stream, ctr);
-    const unsigned blocks = (unsigned)((n + 255) / 256);
+    // element passes: at most 1024 workgroups (one counter atomic each)
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(k_ex_init, dim3(blocks), dim3(256), 0, stream, keys, G, dims[0], dims[1],
                        mask, D, state, above, ctr);
     const dim3 tiles((G.g[0] + EXT - 1) / EXT, (G.g[1] + EXT - 1) / EXT, (G.g[2] + EXT - 1) / EXT);
@@ -1106,7 +1279,8 @@ hipError_t launch_select_ex_large(const void *vol, nrr_dtype dtype, const int32_
 void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const BoxGrid &G,
                  int64_t n, uint64_t *keys, hipStream_t stream) {
     // overlapping candidates (stride below the edge in x or y) whose tile
-    // region fits: the tiled kernel; otherwise one wavefront per candidate
+    // region fits: the tiled kernel; candidates apart in x and y: by grid
+    // rows; otherwise one wavefront per candidate
     const bool overlap = G.s[0] < G.b[0] || G.s[1] < G.b[1];
     const int rx = ((KT - 1) * G.s[0] + G.b[0] + 1) & ~1, ry = (KT - 1) * G.s[1] + G.b[1];
     if (dtype == NRR_U16 && overlap && rx <= KT_MAXR && ry <= KT_MAXR)
@@ -1115,7 +1289,14 @@ void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const 
                                 (unsigned)G.g[2]),
                            dim3(256), (size_t)rx * ry * 2 + (size_t)ry * KT * 8, stream,
                            static_cast<const uint16_t *>(vol), dims[0], dims[1], G, keys);
-    else if (dtype == NRR_U16)
+    else if (dtype == NRR_U16 && !overlap && G.g[1] <= 65535 && G.g[2] <= 65535) {
+        const int cx = (64 - G.b[0]) / G.s[0] + 1;  // candidates of a row per workgroup
+        hipLaunchKernelGGL(k_block_keys_u16_rows,
+                           dim3((unsigned)((G.g[0] + cx - 1) / cx), (unsigned)G.g[1],
+                                (unsigned)G.g[2]),
+                           dim3(256), 0, stream, static_cast<const uint16_t *>(vol), dims[0],
+                           dims[1], G, cx, keys);
+    } else if (dtype == NRR_U16)
         hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
                            static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n, keys);
     else
@@ -1175,12 +1356,12 @@ void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t
         }
         hipLaunchKernelGGL(k_tile_counts, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys,
                            n, st, tiles);
-    } else {  // one workgroup: the K-th key, then the tile counts
+        hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
+                           st, tiles, G, k, kd, centers);
+    } else {  // one workgroup: the K-th key and the compaction
         hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st,
-                           tiles);
+                           G, centers);
     }
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n, st,
-                       tiles, G, k, kd, centers);
 }
 
 hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3],

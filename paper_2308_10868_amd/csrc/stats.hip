@@ -15,20 +15,26 @@
 //        resolve a smaller relative spread from these sums).
 //
 // Layout of the outputs: dense [Oz][Oy][Ox] with O = dims - block + 1 (index =
-// lowest corner of the block).  Work decomposition: a workgroup owns a
-// 64 x 4 tile of (x, y) origins and a run of zc origin planes; each input
-// plane is staged in LDS (fetched two planes ahead) and summed along x
-// (sliding windows over 4-wide segments) then along y; the per-plane sums of
-// the last bz planes sit in a small LDS ring, and the z sum slides exactly
-// (integers) or is re-added from the ring (floating point).  The next plane's patch is fetched into registers
-// while the current one is summed (double-buffered LDS patch).  For 12-bit
-// data the same pass writes the plane-pair volume the search reads (one word
-// per voxel from the staged plane and the next one), each voxel by exactly one
-// workgroup.
+// lowest corner of the block).
+//
+// 12-bit data, by voxel columns: a wavefront owns 64 consecutive voxel
+// columns (x) over the rows of 8 origin rows (y) and slides along a run of
+// origin planes.  Each lane keeps, per row, the sums over the block's current
+// bz planes of F - 2048 and of its square (exact integers: each step adds the
+// plane entering and subtracts the plane leaving, read again), forms the
+// by-row sums in registers and the bx-column sums across lanes through LDS.
+// Wavefronts share no data, so the kernel has no barrier.  The plane-pair
+// volume that the search reads is written by a separate pass.
+//
+// Float data, by tiles: a workgroup owns a 64 x 4 tile of (x, y) origins and
+// a run of zc origin planes; each input plane is staged in LDS (fetched two
+// planes ahead) and summed along x (sliding windows over 4-wide segments)
+// then along y; the per-plane sums of the last bz planes sit in a small LDS
+// ring and the block sums are re-added from it (no rounding drifts along
+// the volume).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-
 #include <type_traits>
 
 #include "nrr_internal.h"
@@ -51,35 +57,29 @@ __device__ inline void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Shared body of the two statistics kernels.  V: staged voxel type, A/AQ:
-// row and plane sums of F and F^2, AS/AQQ: block sums.  SLIDE: integer sums
-// (exact) slide along z; floating sums are re-added from the ring so no
-// rounding drifts along the volume.  Global loads run two planes ahead of
-// the plane being summed.
-template <bool SLIDE, typename V, typename A, typename AQ, typename AS, typename AQQ,
-          typename Src, typename Conv, typename Emit>
+// Body of the float statistics kernel.  V: staged voxel type, A/AQ: row and
+// plane sums of F and F^2, AS/AQQ: block sums, re-added from the ring of the
+// last bz plane sums.  Global loads run two planes ahead of the plane being
+// summed.
+template <typename V, typename A, typename AQ, typename AS, typename AQQ, typename Src,
+          typename Conv, typename Emit>
 __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int bx,
-                                  int by, int bz,
-                                  int ox, int oy, int oz, int zc, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
-                                  A *ringP, AQ *ringQ, uint32_t *__restrict__ pairs, Conv conv,
-                                  Emit emit) {
+                                  int by, int bz, int ox, int oy, int oz, int zc,
+                                  V *patch /*[2][PATCH]*/, A *rs, AQ *rq, A *ringP, AQ *ringQ,
+                                  Conv conv, Emit emit) {
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;  // output (tx, ty)
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
     const int ph = TY + by - 1, pw = TX + bx - 1;
     const int zend = min(z0 + zc + bz - 1, nz);  // input planes [z0, zend)
-    // this thread's patch elements: fixed offsets inside a plane.  pown: the
-    // element's plane-pair word is this workgroup's to write (its own tile,
-    // and the halo on the last tile of an axis, so every voxel has one writer)
+    // this thread's patch elements: fixed offsets inside a plane
     int goff[PER];
-    bool gok[PER], pown[PER];
+    bool gok[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = tid + 256 * k, r = e / pw, c = e - r * pw;
         gok[k] = e < ph * pw && x0 + c < nx && y0 + r < ny;
         goff[k] = r * nx + c;
-        pown[k] = gok[k] && (c < TX || x0 + TX >= ox) && (r < TY || y0 + TY >= oy);
     }
-    const bool lastz = z0 + zc >= oz;  // the last run also owns the planes past its origins
     const int64_t pstride = (int64_t)ny * nx;
     const Src *pbase = flt + (int64_t)y0 * nx + x0;
     // Loads are issued unconditionally (elements outside the volume or past
@@ -108,8 +108,6 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
     for (int k = 0; k < PER; ++k) patch[tid + 256 * k] = value(r1, k);
     fetch(r1, z0 + 1);
     lds_barrier();
-    AS S = 0;
-    AQQ QQ = 0;
     const int nseg = ph * (TX / SEG);
     // one plane step; rn holds plane zi + 1 (fetched a step earlier), rf
     // receives plane zi + 2.  The loop runs two steps per iteration with the
@@ -118,21 +116,6 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
         const int cur = (zi - z0) & 1;
         const V *pc = patch + cur * PATCH;
         fetch(rf, zi + 2);
-        if constexpr (std::is_same<V, int32_t>::value) {
-            // plane-pair words of this plane (rn holds the next plane: the
-            // caller asks for them only when a block spans two planes or more,
-            // so the next plane of an owned one is always fetched)
-            if (pairs && (zi < z0 + zc || lastz)) {
-                uint32_t *pl = pairs + (pbase - flt) + (int64_t)zi * pstride;
-#pragma unroll
-                for (int k = 0; k < PER; ++k)
-                    if (pown[k]) {
-                        const int hi = zi + 1 < nz ? value(rn, k) : 0;
-                        pl[goff[k]] = (uint32_t)(uint16_t)pc[tid + 256 * k] |
-                                      (uint32_t)(uint16_t)hi << 16;
-                    }
-            }
-        }
         // sums along x: SEG outputs per segment by a sliding window
         for (int sg = tid; sg < nseg; sg += 256) {
             const int r = sg / (TX / SEG), xs = (sg % (TX / SEG)) * SEG;
@@ -163,25 +146,16 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
             Q += rq[(ty + k) * TX + tx];
         }
         const int slot = (zi - z0) % bz;
-        if constexpr (SLIDE) {
-            const bool full = zi - z0 >= bz;  // the slot holds the plane leaving the block
-            S += (AS)P - (full ? (AS)ringP[slot * 256 + tid] : (AS)0);
-            QQ += (AQQ)Q - (full ? (AQQ)ringQ[slot * 256 + tid] : (AQQ)0);
-        }
         ringP[slot * 256 + tid] = P;
         ringQ[slot * 256 + tid] = Q;
         if (zi - z0 >= bz - 1) {  // the last bz plane sums give the block sums
             const int z = zi - bz + 1, x = x0 + tx, y = y0 + ty;
             if (x < ox && y < oy && z < oz) {
-                AS sb = S;
-                AQQ qb = QQ;
-                if constexpr (!SLIDE) {
-                    sb = 0;
-                    qb = 0;
-                    for (int k = 0; k < bz; ++k) {
-                        sb += (AS)ringP[k * 256 + tid];
-                        qb += (AQQ)ringQ[k * 256 + tid];
-                    }
+                AS sb = 0;
+                AQQ qb = 0;
+                for (int k = 0; k < bz; ++k) {
+                    sb += (AS)ringP[k * 256 + tid];
+                    qb += (AQQ)ringQ[k * 256 + tid];
                 }
                 emit(((int64_t)z * oy + y) * ox + x, sb, qb);
             }
@@ -197,30 +171,147 @@ __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, i
     }
 }
 
+// Workgroup-free LDS ordering between the lanes of one wavefront: its LDS
+// writes complete before the reads that follow.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int SC_RY = 8;        // origin rows per wavefront
+constexpr int SC_LW = 64 + 16;  // LDS slots of a row: the lanes, then the x reach
+constexpr int SC_WAVES = 8192;  // wavefronts a launch aims at (z-runs are cut to reach it)
+
+// 12-bit statistics by voxel columns (see the top of the file).  BY: block
+// edge in y; BC: the cubic block edge when it is known at compile time (then
+// bx = bz = BY = BC), 0 when bx and bz come at run time.  Lanes 0 .. 64 - bx
+// hold origins x0 + lane.
+template <int BY, int BC>
 __global__ __launch_bounds__(256) void k_stats_u16(const uint16_t *__restrict__ flt, int nx,
-                                                   int ny, int nz, int bx, int by, int bz, int ox,
+                                                   int ny, int nz, int bx_rt, int bz_rt, int ox,
                                                    int oy, int oz, int zc,
-                                                   StatU16 *__restrict__ out,
-                                                   uint32_t *__restrict__ pairs) {
-    __shared__ int32_t patch[2 * PATCH + 256];
-    __shared__ int32_t rs[PH * TX];
-    __shared__ uint32_t rq[PH * TX];
-    // ring of the last bz per-plane sums, [bz][256] each (dynamic LDS)
-    extern __shared__ __align__(16) unsigned char dyn_u16[];
-    int32_t *ringP = reinterpret_cast<int32_t *>(dyn_u16);
-    uint32_t *ringQ = reinterpret_cast<uint32_t *>(dyn_u16 + (size_t)bz * 256 * 4);
-    const int64_t n = (int64_t)bx * by * bz;
-    stats_body<true, int32_t, int32_t, uint32_t, int32_t, uint64_t>(
-        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, pairs,
-        [](uint16_t v) { return (int32_t)v - 2048; },
-        [&](int64_t o, int32_t S, uint64_t QQ) {
-            const int64_t var = n * (int64_t)QQ - (int64_t)S * S;
-            // r ranks displacements only (the reported NCC is recomputed exactly)
-            StatU16 rec;
-            rec.s = S;
-            rec.r = var > 0 ? rsqrtf((float)var) : 0.0f;
-            out[o] = rec;
-        });
+                                                   StatU16 *__restrict__ out) {
+    static_assert(BC == 0 || BC == BY, "a cubic block has one edge");
+    constexpr int RY = SC_RY, NR = RY + BY - 1;  // origin rows, voxel rows
+    // block sums of squares fit 32 bits when N 2048^2 < 2^32 (N <= 1023)
+    constexpr bool Q32 = BC != 0 && BC * BC * BC <= 1023;
+    using QT = typename std::conditional<Q32, uint32_t, uint64_t>::type;
+    const int bx = BC ? BC : bx_rt, bz = BC ? BC : bz_rt;
+    __shared__ uint2 xch[4][RY][SC_LW];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int txw = 65 - bx;  // origins per wavefront in x
+    const int x0 = blockIdx.x * txw;
+    const int y0 = (blockIdx.y * 4 + w) * RY;
+    if (y0 >= oy) return;  // whole wavefront leaves together
+    const int z0 = blockIdx.z * zc, zend = min(z0 + zc, oz);
+    const int x = min(x0 + lane, nx - 1);  // lanes past the volume read its last column
+    const int64_t ps = (int64_t)nx * ny;
+    // voxel row r of this wavefront in plane p (rows past the volume read its last)
+    auto load_plane = [&](uint32_t(&v)[NR], int p) {
+        const uint16_t *pl = flt + (int64_t)min(p, nz - 1) * ps + x;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) v[r] = pl[(int64_t)min(y0 + r, ny - 1) * nx];
+    };
+    int32_t zs[NR];
+    uint32_t zq[NR];  // <= 15 squares of 2048^2: < 2^32
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        zs[r] = 0;
+        zq[r] = 0;
+    }
+    auto add_plane = [&](const uint32_t(&v)[NR]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int d = (int)v[r] - 2048;
+            zs[r] += d;
+            zq[r] += (uint32_t)(d * d);
+        }
+    };
+    // the first origin plane's bz planes, the next plane in flight while one
+    // is added (two buffers, so no register copy waits on a load)
+    uint32_t va[NR], vb[NR];
+    load_plane(va, z0);
+    for (int p = 0; p < bz; p += 2) {
+        load_plane(vb, z0 + p + 1);
+        add_plane(va);
+        load_plane(va, z0 + p + 2);
+        if (p + 1 < bz) add_plane(vb);
+    }
+    const double n = (double)(bx * BY * bz);
+    const bool xin = lane < txw && x0 + lane < ox;
+    for (int z = z0; z < zend; ++z) {
+        // the planes entering (z + bz) and leaving (z) at the next origin
+        // plane, in flight while this one is summed
+        load_plane(va, z + bz);
+        load_plane(vb, z);
+        // by-row sums (sliding over the rows, exact)
+        int32_t vs[RY];
+        uint32_t vq[RY];
+        {
+            int32_t a = 0;
+            uint32_t b = 0;
+#pragma unroll
+            for (int k = 0; k < BY; ++k) {
+                a += zs[k];
+                b += zq[k];
+            }
+            vs[0] = a;
+            vq[0] = b;
+#pragma unroll
+            for (int r = 1; r < RY; ++r) {
+                a += zs[r + BY - 1] - zs[r - 1];
+                b += zq[r + BY - 1] - zq[r - 1];
+                vs[r] = a;
+                vq[r] = b;
+            }
+        }
+        // bx-column sums across lanes
+        wave_lds_sync();  // the previous plane's reads are done
+#pragma unroll
+        for (int r = 0; r < RY; ++r) xch[w][r][lane] = make_uint2((uint32_t)vs[r], vq[r]);
+        wave_lds_sync();
+        StatU16 *orow = out + ((int64_t)z * oy + y0) * ox + x0;  // origin (x0, y0, z)
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const uint2 *row = &xch[w][r][lane];
+            int32_t S = 0;
+            QT Q = 0;
+            if constexpr (BC != 0) {
+#pragma unroll
+                for (int k = 0; k < BC; ++k) {
+                    const uint2 u = row[k];
+                    S += (int32_t)u.x;
+                    Q += u.y;
+                }
+            } else {
+                for (int k = 0; k < bx; ++k) {
+                    const uint2 u = row[k];
+                    S += (int32_t)u.x;
+                    Q += u.y;
+                }
+            }
+            if (xin && y0 + r < oy) {
+                // N q - s^2 < 2^53: exact in FP64, then rounded once to float
+                // (the same value as rounding the integer)
+                const double var = fma(n, (double)Q, -((double)S * (double)S));
+                // r ranks displacements only (the reported NCC is recomputed exactly)
+                StatU16 rec;
+                rec.s = S;
+                rec.r = var > 0.0 ? rsqrtf((float)var) : 0.0f;
+                orow[(int64_t)r * ox + lane] = rec;
+            }
+        }
+        // slide the z sums to the next origin plane
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            // (e - 2048)^2 - (l - 2048)^2 = (e - l)(e + l - 4096), |each| < 2^12
+            const int t = (int)va[r] - (int)vb[r];
+            zs[r] += t;
+            zq[r] += (uint32_t)(t * ((int)va[r] + (int)vb[r] - 4096));
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt, int nx, int ny,
@@ -233,8 +324,8 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
     double *ringP = reinterpret_cast<double *>(dyn_f32);
     double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)bz * 256 * 8);
     const double n = (double)bx * by * bz;
-    stats_body<false, float, double, double, double, double>(
-        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ, nullptr,
+    stats_body<float, double, double, double, double>(
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
         [](float v) { return v; },
         [&](int64_t o, double S, double QQ) {
             const double nq = n * QQ;
@@ -249,8 +340,6 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
 // Plane-pair copy of a 12-bit volume: one 4-byte word per voxel holding the
 // voxel and the one a plane above, both offset by -2048 into int16 (the next
 // plane's half is 0 on the last plane).  Four consecutive voxels per thread.
-// The statistics kernel writes the same words as it goes; this kernel serves
-// blocks one plane thick.
 __global__ __launch_bounds__(256) void k_pair_volume(const uint16_t *__restrict__ flt,
                                                      int64_t nvox, int64_t pstride,
                                                      uint32_t *__restrict__ out) {
@@ -378,6 +467,46 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     StatsLayout L = stats_layout(dtype, dims, block, pairs);
     char *ws = static_cast<char *>(workspace);
     const int bx = block[0], by = block[1], bz = block[2];
+    if (dtype == NRR_U16) {
+        // z-runs cut so that the launch has about SC_WAVES wavefronts
+        const int txw = 65 - bx;
+        const int64_t nwx = (L.ox + txw - 1) / txw, nwy = (L.oy + SC_RY - 1) / SC_RY;
+        int64_t runs = (SC_WAVES + nwx * nwy - 1) / (nwx * nwy);
+        runs = runs < 1 ? 1 : (runs > L.oz ? L.oz : runs);
+        const int zc = (int)((L.oz + runs - 1) / runs);
+        const dim3 grid((unsigned)nwx, (unsigned)((nwy + 3) / 4), (unsigned)((L.oz + zc - 1) / zc));
+        StatU16 *out = reinterpret_cast<StatU16 *>(ws);
+        const uint16_t *f = static_cast<const uint16_t *>(flt);
+        switch (by) {
+#define NRR_STATS_BY(BY)                                                                         \
+    case BY:                                                                                     \
+        if (bx == BY && bz == BY)                                                                \
+            hipLaunchKernelGGL((k_stats_u16<BY, BY>), grid, dim3(256), 0, stream, f, dims[0],    \
+                               dims[1], dims[2], bx, bz, L.ox, L.oy, L.oz, zc, out);             \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_stats_u16<BY, 0>), grid, dim3(256), 0, stream, f, dims[0],     \
+                               dims[1], dims[2], bx, bz, L.ox, L.oy, L.oz, zc, out);             \
+        break;
+            NRR_STATS_BY(1)
+            NRR_STATS_BY(3)
+            NRR_STATS_BY(5)
+            NRR_STATS_BY(7)
+            NRR_STATS_BY(9)
+            NRR_STATS_BY(11)
+            NRR_STATS_BY(13)
+            NRR_STATS_BY(15)
+#undef NRR_STATS_BY
+        default:
+            return hipErrorInvalidValue;  // block edges are odd, 1 .. 15
+        }
+        if (L.pair_off) {
+            const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+            hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)((nvox + 1023) / 1024)), dim3(256), 0,
+                               stream, f, nvox, (int64_t)dims[0] * dims[1],
+                               reinterpret_cast<uint32_t *>(ws + L.pair_off));
+        }
+        return hipGetLastError();
+    }
     // origin planes per workgroup: ZC, fewer when that leaves the device with
     // too few workgroups (small volumes), never below 4
     const int64_t per_slab = (int64_t)((L.ox + TX - 1) / TX) * ((L.oy + TY - 1) / TY);
@@ -390,24 +519,9 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
     const int runs = (L.oz + zc - 1) / zc;
     zc = (L.oz + runs - 1) / runs;
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
-    if (dtype == NRR_U16) {
-        uint32_t *pairs =
-            L.pair_off && bz >= 2 ? reinterpret_cast<uint32_t *>(ws + L.pair_off) : nullptr;
-        hipLaunchKernelGGL(k_stats_u16, grid, dim3(256), (size_t)bz * 256 * 8, stream,
-                           static_cast<const uint16_t *>(flt), dims[0], dims[1], dims[2], bx, by,
-                           bz, L.ox, L.oy, L.oz, zc, reinterpret_cast<StatU16 *>(ws), pairs);
-        if (L.pair_off && !pairs) {
-            const int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
-            const int64_t groups = (nvox + 1023) / 1024;
-            hipLaunchKernelGGL(k_pair_volume, dim3((unsigned)groups), dim3(256), 0, stream,
-                               static_cast<const uint16_t *>(flt), nvox,
-                               (int64_t)dims[0] * dims[1],
-                               reinterpret_cast<uint32_t *>(ws + L.pair_off));
-        }
-    } else
-        hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
-                           static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
-                           L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
+    hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
+                       static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
+                       L.ox, L.oy, L.oz, zc, reinterpret_cast<StatF32 *>(ws));
     return hipGetLastError();
 }
 

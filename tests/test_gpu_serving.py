@@ -213,7 +213,14 @@ def test_admission_respects_device_memory(torch_dev, mix):
     out, infos, st = serve(mix, slots=6, device_bytes=budget)
     assert st["completed"] == len(mix) and st["pending"] == 0
     assert st["peak_bytes"] <= budget
-    assert 1 <= st["max_running"] <= 3, st
+    # most requests that fit the budget at once: the smallest footprints first
+    fit, used = 0, 0
+    for b in sorted(fp):
+        if used + b > budget:
+            break
+        fit, used = fit + 1, used + b
+    assert fit < len(mix)  # the budget does bound admission
+    assert 1 <= st["max_running"] <= fit, st
     alone, _, _ = serve(mix, slots=1, device_bytes=1 << 30, one_at_a_time=True)
     for a, m in zip(alone, out):
         for x, y in zip(a, m):

@@ -72,6 +72,71 @@ def test_statistics_table_and_pair_volume(dims, b, seed):
     assert np.array_equal(pairs, lo | hi << 16)
 
 
+def check_u16_records(raw, v, block):
+    """Records {int32 s, float32 r} of a 12-bit table against box sums of v."""
+    bx, by, bz = block
+    nz, ny, nx = v.shape
+    ox, oy, oz = nx - bx + 1, ny - by + 1, nz - bz + 1
+    f = v.astype(np.int64) - 2048
+    s_want = box_sum3(f, block)
+    q_want = box_sum3(f * f, block)
+    rec = raw[:ox * oy * oz * 8].view(np.int32).reshape(oz, oy, ox, 2)
+    assert np.array_equal(rec[..., 0], s_want)
+    var = bx * by * bz * q_want - s_want * s_want
+    r_want = np.zeros(var.shape)
+    r_want[var > 0] = 1.0 / np.sqrt(var[var > 0].astype(np.float64))
+    r_got = rec[..., 1].copy().view(np.float32).astype(np.float64)
+    assert np.all((r_got == 0) == (r_want == 0))
+    assert np.allclose(r_got, r_want, rtol=2e-6, atol=0)
+
+
+def box_sum3(v, block):
+    """Sum over every bx x by x bz box of v ([z][y][x]), by its lowest corner."""
+    bx, by, bz = block
+    c = np.zeros(tuple(n + 1 for n in v.shape), np.int64)
+    c[1:, 1:, 1:] = v.cumsum(0).cumsum(1).cumsum(2)
+    return (c[bz:, by:, bx:] - c[:-bz, by:, bx:] - c[bz:, :-by, bx:] - c[bz:, by:, :-bx]
+            + c[:-bz, :-by, bx:] + c[:-bz, by:, :-bx] + c[bz:, :-by, :-bx]
+            - c[:-bz, :-by, :-bx])
+
+
+@pytest.mark.parametrize("dims,block,seed", [((70, 40, 30), (3, 7, 5), 11),
+                                             ((90, 33, 20), (15, 1, 3), 12),
+                                             ((64, 70, 25), (1, 15, 9), 13),
+                                             ((130, 50, 18), (5, 11, 1), 14),
+                                             ((66, 41, 16), (13, 9, 15), 15)])
+def test_statistics_table_per_axis_blocks(dims, block, seed):
+    """The table of a per-axis block (nrr_window_stats_aniso: records only)."""
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    v = np.random.default_rng(seed).integers(0, 4096, size=dims[::-1]).astype(np.uint16)
+    v[0, 0, :4] = [0, 4095, 0, 4095]
+    say("per-axis stats table", dims, block)
+    ws = nrr.window_stats_aniso(to_dev(v), block)
+    torch.cuda.synchronize()
+    check_u16_records(ws.cpu().numpy(), v, block)
+
+
+@pytest.mark.parametrize("dims,b,seed", [((700, 600, 40), 3, 21), ((1024, 800, 40), 15, 22)])
+def test_statistics_table_long_z_runs(dims, b, seed):
+    """Volumes wide enough in x and y that a launch gives each wavefront
+    several origin planes, so the z sums slide (plane entering added, plane
+    leaving subtracted) over several steps; a flat slab and the 12-bit
+    extremes on top of uniform noise."""
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    v = np.random.default_rng(seed).integers(0, 4096, size=dims[::-1]).astype(np.uint16)
+    v[5:25, 100:140, 200:260] = 1234  # flat windows: r = 0
+    v[30:33, :, :3] = 4095
+    v[31, 7, :] = 0
+    say("long-run stats table", dims, b)
+    ws = nrr.window_stats(to_dev(v), b)
+    torch.cuda.synchronize()
+    check_u16_records(ws.cpu().numpy(), v, (b, b, b))
+
+
 def test_check_volume_counts_voxels_outside_the_contract():
     """nrr_check_volume: 12-bit voxels above 4095 and non-finite floats."""
     import torch
