@@ -337,21 +337,27 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
         }
         // the lane's four output rows: displacement (odx, ody) relative to the
         // valid range's corner, plane offset oph; records at orec + dz planes
-        int odx[4], ody[4], oph[4], orec[4], oxy[4];
-        bool orow[4];
+        // ranking of plane tau: valid while tau < lim (lim = -1 for rows
+        // outside the valid range), shift index oidx + tau side^2; records
+        // of plane min(tau + oph, dzn - 1) at rcur, which advances by a plane
+        // while tau < lim3 = dzn - 1 - oph
+        int rcur[4], lim[4], lim3[4], oidx[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int r = 16 * tile + 4 * grp + i;
-            orow[i] = r < tl.nrows;
-            const int rr = orow[i] ? r : 0;
+            bool orow = r < tl.nrows;
+            const int rr = orow ? r : 0;
             const int xy = rr % tl.nxy, ph = rr / tl.nxy;
-            odx[i] = 4 * (xy % tl.nbx) + oa - g.px;
-            ody[i] = 4 * (xy / tl.nbx) + ob;
-            oph[i] = ph * tl.tz;
-            orow[i] = orow[i] && odx[i] >= 0 && odx[i] < g.dxn && ody[i] < g.dyn;
-            orec[i] = (g.wz0 * p.oy + (g.wy0 + min(ody[i], g.dyn - 1))) * p.ox +
-                      (g.wx0 + min(max(odx[i], 0), g.dxn - 1));
-            oxy[i] = (g.loy + ody[i] + p.w) * side + (g.lox + odx[i] + p.w);
+            const int odx = 4 * (xy % tl.nbx) + oa - g.px;
+            const int ody = 4 * (xy / tl.nbx) + ob;
+            const int oph = ph * tl.tz;
+            orow = orow && odx >= 0 && odx < g.dxn && ody < g.dyn;
+            rcur[i] = (g.wz0 * p.oy + (g.wy0 + min(ody, g.dyn - 1))) * p.ox +
+                      (g.wx0 + min(max(odx, 0), g.dxn - 1)) + min(oph, g.dzn - 1) * plane_rec;
+            lim[i] = orow ? g.dzn - oph : -1;
+            lim3[i] = g.dzn - 1 - oph;
+            oidx[i] = (g.loz + oph + p.w) * side2 + (g.loy + ody + p.w) * side +
+                      (g.lox + odx + p.w);
         }
         float4v acc[B];
 #pragma unroll
@@ -374,22 +380,35 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
         StatU16 rec0[4];
         auto fetch = [&](int tau, StatU16 (&rec)[4]) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                rec[i] = p.stats[orec[i] + min(tau + oph[i], g.dzn - 1) * plane_rec];
+            for (int i = 0; i < 4; ++i) {
+                rec[i] = p.stats[rcur[i]];
+                rcur[i] += tau < lim3[i] ? plane_rec : 0;
+            }
         };
+        // best key of each output row in this tile and its plane (-1: none).
+        // Along a row the shift index grows with tau, so a strict comparison
+        // keeps the smallest index among equal keys; rows are merged with the
+        // full rule after the tile.
+        float rk[4];
+        int rt[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            rk[i] = -INFINITY;
+            rt[i] = -1;
+        }
         // ranking of displacement plane tau, then the records of tau + 1
         auto rank = [&](const float4v &c4, int tau) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int dz = tau + oph[i];
                 const float sts = __builtin_fmaf(fST, (float)rec0[i].s, fshift);
                 const float cov = __builtin_fmaf(fN, c4[i], -sts);
-                const bool valid = orow[i] && dz < g.dzn;
-                const float key = valid ? cov * rec0[i].r : -INFINITY;
-                const int idx = valid ? (g.loz + dz + p.w) * side2 + oxy[i] : INT_MAX;
-                keep_best(bk, bi, key, idx);
+                const float key = cov * rec0[i].r;
+                const bool take = (tau < lim[i]) & (key > rk[i]);
+                rk[i] = take ? key : rk[i];
+                rt[i] = take ? tau : rt[i];
                 if constexpr (SURF)  // NCC = key / sqrt(N varT)
-                    if (valid) p.surface[blk * side2 * side + idx] = key * inv_vt;
+                    if (tau < lim[i]) p.surface[blk * side2 * side + oidx[i] + tau * side2] =
+                        key * inv_vt;
             }
             fetch(tau + 1, rec0);
         };
@@ -399,6 +418,9 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
         sweep_block<B, NQ, 0>(0, acc, bop, aop, load_a, rank);
         for (int t0 = B; t0 < tl.tz; t0 += B) sweep_block<B, NQ, 1>(t0, acc, bop, aop, load_a, rank);
         sweep_block<B, NQ, 2>(tl.tz, acc, bop, aop, load_a, rank);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (rt[i] >= 0) keep_best(bk, bi, rk[i], oidx[i] + rt[i] * side2);
     }
 }
 
