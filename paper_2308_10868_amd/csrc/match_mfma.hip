@@ -385,17 +385,15 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
                 rcur[i] += tau < lim3[i] ? plane_rec : 0;
             }
         };
-        // best key of each output row in this tile and its plane (-1: none).
-        // Along a row the shift index grows with tau, so a strict comparison
-        // keeps the smallest index among equal keys; rows are merged with the
-        // full rule after the tile.
+        // best key of each output row in this tile and its plane (byte i of
+        // rtp; 0xff: none; planes < 255, see mf_plan).  Along a row the shift
+        // index grows with tau, so a strict comparison keeps the smallest
+        // index among equal keys; rows are merged with the full rule after
+        // the tile.
         float rk[4];
-        int rt[4];
+        uint32_t rtp = 0xffffffffu;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            rk[i] = -INFINITY;
-            rt[i] = -1;
-        }
+        for (int i = 0; i < 4; ++i) rk[i] = -INFINITY;
         // ranking of displacement plane tau, then the records of tau + 1
         auto rank = [&](const float4v &c4, int tau) {
 #pragma unroll
@@ -405,7 +403,7 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
                 const float key = cov * rec0[i].r;
                 const bool take = (tau < lim[i]) & (key > rk[i]);
                 rk[i] = take ? key : rk[i];
-                rt[i] = take ? tau : rt[i];
+                rtp = take ? (rtp & ~(0xffu << (8 * i))) | ((uint32_t)tau << (8 * i)) : rtp;
                 if constexpr (SURF)  // NCC = key / sqrt(N varT)
                     if (tau < lim[i]) p.surface[blk * side2 * side + oidx[i] + tau * side2] =
                         key * inv_vt;
@@ -419,8 +417,10 @@ __device__ __attribute__((always_inline)) inline void sweep_tiles(
         for (int t0 = B; t0 < tl.tz; t0 += B) sweep_block<B, NQ, 1>(t0, acc, bop, aop, load_a, rank);
         sweep_block<B, NQ, 2>(tl.tz, acc, bop, aop, load_a, rank);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (rt[i] >= 0) keep_best(bk, bi, rk[i], oidx[i] + rt[i] * side2);
+        for (int i = 0; i < 4; ++i) {
+            const int rt = (rtp >> (8 * i)) & 0xff;
+            if (rt != 0xff) keep_best(bk, bi, rk[i], oidx[i] + rt * side2);
+        }
     }
 }
 
@@ -728,6 +728,7 @@ bool mf_plan(int b, int w, size_t limit, MfPlan *out) {
     int pl = py * rp;
     if (((pl * 2) % 256) == 0) pl += 8;
     const int planes = d + b - 1;
+    if (planes >= 255) return false;  // the ranking keeps plane numbers in bytes
     const size_t lds = (size_t)v->tt_bytes + (size_t)planes * pl * 2;
     if (lds + sizeof(MfSmall) > limit) return false;
     out->rp = rp;
