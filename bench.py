@@ -272,23 +272,21 @@ def main() -> int:
     ncc = torch.empty(k, dtype=torch.float32, device=dev)
     conf = torch.empty(k, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
-    side = torch.cuda.Stream(dev)  # default priority
 
     def step(ev=None):
         # selection (reads ref) and the window statistics (read flt) are
-        # independent: the statistics run on a second stream, after the
-        # previous step's search has released the table.  ev: events around
-        # the selection and around the search, all on the main stream.
-        side.wait_stream(stream)
-        with torch.cuda.stream(side):
-            nrr.window_stats(flt, b, workspace=mat_ws, window=w)
+        # independent: one library call runs the statistics on its second
+        # stream beside the selection, forked after the keys kernel (so the
+        # selection's one-workgroup kernel is placed first) and joined back
+        # before the search; being on this stream, they follow the previous
+        # step's search, which releases the table.  ev: events around the
+        # selection + statistics and around the search, on this stream.
         if ev is not None:
             ev[0].record(stream)
-        centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
+        centers, _ = nrr.select_and_window_stats(ref, flt, b, stride, frac, w,
+                                                 select_workspace=sel_ws, match_workspace=mat_ws)
         if ev is not None:
             ev[1].record(stream)
-        stream.wait_stream(side)
-        if ev is not None:
             ev[2].record(stream)
         nrr.block_match(ref, flt, centers, b, w, workspace=mat_ws, out=(disp, ncc, conf),
                         prepared=True)
@@ -337,12 +335,9 @@ def main() -> int:
             ref_disp = disp.clone()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                cap = torch.cuda.current_stream()
-                side.wait_stream(cap)
-                with torch.cuda.stream(side):
-                    nrr.window_stats(flt, b, workspace=mat_ws, window=w)
-                g_centers = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
-                cap.wait_stream(side)
+                g_centers, _ = nrr.select_and_window_stats(ref, flt, b, stride, frac, w,
+                                                           select_workspace=sel_ws,
+                                                           match_workspace=mat_ws)
             torch.cuda.synchronize()
 
             def gstep(ev=None):
@@ -432,8 +427,8 @@ def main() -> int:
         "search_kernel_ms_median": float(np.median(search_ms)),
         "search_pairs_per_s": pairs / (kern_ms * 1e-3),
         "selection_ms": {"mean": float(np.mean(select_ms)), "median": float(np.median(select_ms)),
-                         "what": "select_blocks on the main stream, beside the window "
-                                 "statistics on the second (eager steps)"},
+                         "what": "selection and window statistics, side by side in one "
+                                 "call (nrr_select_and_window_stats), eager steps"},
         "search_arith": arith,
         "roofline": roofline,
         "paper_context": PAPER_CONTEXT,

@@ -208,6 +208,26 @@ nrr_status nrr_window_stats(const void *flt, nrr_dtype dtype, const int32_t dims
                             int32_t block, void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* Selection and window statistics of one step in one call: the plain
+ * selection of `ref` (exactly nrr_select_blocks: the same K, centres and
+ * errors) and the statistics of `flt` that the search for `window` reads
+ * (exactly nrr_window_stats_for), the two running side by side.  The keys
+ * kernel goes on `stream`; the statistics go on a second stream of this
+ * library (one per device, default priority, created on first use), forked
+ * from `stream` after the keys so that the selection's one-workgroup kernel
+ * is placed before the statistics fill the device; `stream` waits for both
+ * before any later work.  Safe under stream capture (the second stream joins
+ * the capture and is joined back).  Concurrent calls on one device are
+ * serialised while they enqueue; a call made while another host thread
+ * captures a graph on the same device fails.  Errors as the two calls, plus
+ * UNSUPPORTED for device indices of 64 or more. */
+nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dtype dtype,
+                                       const int32_t dims[3], int32_t block, int32_t stride,
+                                       double fraction, int32_t window, int32_t *centers,
+                                       int64_t capacity, int64_t *k_out, void *select_workspace,
+                                       size_t select_workspace_bytes, void *match_workspace,
+                                       size_t match_workspace_bytes, void *stream);
+
 /* nrr_window_stats_for: as nrr_window_stats, for the search that nrr_block_match_prepared will run
  * with this window under the current plan (nrr_match_plan): the plane-pair
  * volume of 12-bit data is written only when that search reads it (the

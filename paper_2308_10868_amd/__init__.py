@@ -141,6 +141,8 @@ def load():
         "nrr_select_blocks_static": (st, [P, ctypes.c_int, P, I32, I32, F64, P, I64, P, P]),
         "nrr_window_stats": (st, [P, ctypes.c_int, P, I32, P, SZ, P]),
         "nrr_window_stats_for": (st, [P, ctypes.c_int, P, I32, I32, P, SZ, P]),
+        "nrr_select_and_window_stats": (st, [P, P, ctypes.c_int, P, I32, I32, F64, I32, P, I64,
+                                             P, P, SZ, P, SZ, P]),
         "nrr_check_volume": (st, [P, ctypes.c_int, P, P, P]),
         "nrr_block_match_prepared": (st, [P, P, ctypes.c_int, P, P, I64, I32, I32, P, P, P, P, SZ,
                                           P]),
@@ -306,6 +308,31 @@ def select_blocks(vol, block: int, stride: int, fraction: float, workspace=None)
                                  ctypes.byref(kout), ctypes.c_void_p(ws.data_ptr()),
                                  ws.numel(), _stream(vol)))
     return out[:kout.value]
+
+
+def select_and_window_stats(ref, flt, block: int, stride: int, fraction: float, window: int,
+                            select_workspace=None, match_workspace=None):
+    """select_blocks(ref, ...) and window_stats(flt, block, window=window) in
+    one call, side by side on two streams (nrr_select_and_window_stats).
+    Returns (centres int32 [K, 3], the match workspace) on the current
+    stream, which has joined the statistics' stream."""
+    torch = _torch()
+    lib = load()
+    dt, dims = _vol_info(ref)
+    dt2, dims2 = _vol_info(flt)
+    if dt != dt2 or dims != dims2 or ref.device != flt.device:
+        raise NrrError(1, "ref and flt must share dtype, shape and device")
+    k = select_count(dims, block, stride, fraction)
+    out = torch.empty((max(k, 1), 3), dtype=torch.int32, device=ref.device)
+    sws = _workspace(select_workspace_bytes(dims, block, stride), ref.device, select_workspace)
+    mws = _workspace(match_workspace_bytes(dt, dims, block), ref.device, match_workspace)
+    kout = ctypes.c_int64()
+    _check(lib.nrr_select_and_window_stats(
+        ctypes.c_void_p(ref.data_ptr()), ctypes.c_void_p(flt.data_ptr()), dt, _dims3(dims),
+        block, stride, float(fraction), int(window), ctypes.c_void_p(out.data_ptr()),
+        out.shape[0], ctypes.byref(kout), ctypes.c_void_p(sws.data_ptr()), sws.numel(),
+        ctypes.c_void_p(mws.data_ptr()), mws.numel(), _stream(ref)))
+    return out[:kout.value], mws
 
 
 def select_blocks_ex(vol, block: int, stride: int, fraction: float, mask=None,

@@ -451,6 +451,94 @@ nrr_status nrr_window_stats_for(const void *flt, nrr_dtype dtype, const int32_t 
                       "window statistics launch");
 }
 
+namespace {
+
+// The library's second stream and fork/join events, one set per device,
+// created on first use; the mutex makes each call's record/wait sequence
+// atomic, so the reused events always pair with the call that recorded them.
+struct ForkSet {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_fork_mu;
+ForkSet g_fork[64];
+
+}  // namespace
+
+nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dtype dtype,
+                                       const int32_t dims[3], int32_t block, int32_t stride,
+                                       double fraction, int32_t window, int32_t *centers,
+                                       int64_t capacity, int64_t *k_out, void *select_workspace,
+                                       size_t select_workspace_bytes, void *match_workspace,
+                                       size_t match_workspace_bytes, void *stream) {
+    nrr_status s = check_dtype(dtype);
+    if (s != NRR_OK) return s;
+    if (!k_out) return fail(NRR_ERR_INVALID_ARG, "k_out is NULL");
+    int32_t g[3];
+    if ((s = check_grid(dims, block, stride, g)) != NRR_OK) return s;
+    if (block > 15) return fail(NRR_ERR_UNSUPPORTED, "block edge above 15 is not built");
+    if (!(fraction > 0.0) || fraction > 1.0)
+        return fail(NRR_ERR_INVALID_ARG, "fraction must be in (0, 1] (got %g)", fraction);
+    if (window < 0) return fail(NRR_ERR_INVALID_ARG, "window must be >= 0 (got %d)", window);
+    const int64_t n = (int64_t)g[0] * g[1] * g[2];
+    if (n >= (1ll << 31))
+        return fail(NRR_ERR_UNSUPPORTED, "%lld candidates (grids of 2^31 or more are not built)",
+                    (long long)n);
+    const int64_t k = count_rule(n, fraction);
+    *k_out = k;
+    if (capacity < k)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "capacity %lld < K = %lld", (long long)capacity,
+                    (long long)k);
+    if (!ref || !flt || !match_workspace || (k > 0 && (!centers || !select_workspace)))
+        return fail(NRR_ERR_INVALID_ARG, "volumes, centers and workspaces must be non-NULL");
+    const size_t need = nrr::select_layout(n).total;
+    if (k > 0 && select_workspace_bytes < need)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "selection workspace %zu < %zu bytes",
+                    select_workspace_bytes, need);
+    const nrr::StatsLayout L = nrr::stats_layout(dtype, dims, block);
+    if (match_workspace_bytes < L.total)
+        return fail(NRR_ERR_BUFFER_TOO_SMALL, "match workspace %zu < %zu bytes",
+                    match_workspace_bytes, L.total);
+    const nrr::MatchArgs a = match_args(nullptr, flt, dims, nullptr, 0, block, window, nullptr,
+                                        nullptr, nullptr, match_workspace, L);
+    const bool pairs = plan_reads_pairs(dtype, a);
+    note_pairs(match_workspace, pairs);
+    const int32_t b3[3] = {block, block, block};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e, "device query");
+    if (dev < 0 || dev >= 64) return fail(NRR_ERR_UNSUPPORTED, "device index %d (0..63 built)", dev);
+    std::lock_guard<std::mutex> lk(g_fork_mu);
+    ForkSet &fs = g_fork[dev];
+    if (!fs.side) {
+        e = hipStreamCreateWithFlags(&fs.side, hipStreamNonBlocking);  // default priority
+        // the events order work of this device only: no system-scope fences
+        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.fork, fl);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.join, fl);
+        if (e != hipSuccess) return hip_status(e, "second stream creation");
+    }
+    // keys on `stream`; then the statistics on the second stream (forked
+    // here, so the selection's one-workgroup kernel, next on `stream`, is
+    // placed before the statistics fill the device); `stream` joins them
+    const nrr::BoxGrid G = nrr::cubic_grid(block, stride, g);
+    const nrr::SelectLayout SL = nrr::select_layout(n);
+    char *sws = static_cast<char *>(select_workspace);
+    uint64_t *keys = k > 0 ? reinterpret_cast<uint64_t *>(sws + SL.keys_off) : nullptr;
+    if (k > 0) nrr::launch_keys(ref, dtype, dims, G, n, keys, st);
+    e = hipEventRecord(fs.fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(fs.side, fs.fork, 0);
+    if (e == hipSuccess) e = nrr::launch_stats(flt, dtype, dims, b3, pairs, match_workspace, fs.side);
+    if (e == hipSuccess) e = hipEventRecord(fs.join, fs.side);
+    if (e == hipSuccess && k > 0) {
+        nrr::select_from_keys(keys, n, G, k, nullptr, centers, SL, sws, st);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, fs.join, 0);
+    return hip_status(e, "selection and window statistics launch");
+}
+
 nrr_status nrr_block_match_prepared(const void *ref, const void *flt, nrr_dtype dtype,
                                     const int32_t dims[3], const int32_t *centers, int64_t n,
                                     int32_t block, int32_t window, int32_t *disp, float *ncc,

@@ -1,0 +1,90 @@
+"""GPU: nrr_select_and_window_stats (selection and window statistics side by
+side on two streams) gives exactly what the two separate calls give, eagerly
+and replayed from a captured HIP graph."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2308_10868_amd as nrr
+from paper_2308_10868_amd import synth
+from tests.gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+TILE_SLACK = 16
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def defined_bytes(ws, dims, b, dtype, pairs):
+    """The written parts of a match workspace: the table's records, then the
+    plane-pair words when the plan reads them."""
+    nx, ny, nz = dims
+    ox, oy, oz = nx - b + 1, ny - b + 1, nz - b + 1
+    rec = 8 if dtype == "u16" else 16
+    parts = [ws[:ox * oy * oz * rec]]
+    if pairs:
+        table = ((ox * oy * oz + TILE_SLACK * (ox + 1)) * rec + 255) // 256 * 256
+        parts.append(ws[table:table + 4 * nx * ny * nz])
+    return parts
+
+
+@pytest.mark.parametrize("kind,dims,b,w,frac,seed", [
+    ("u16", (96, 80, 64), 7, 6, 0.25, 1),     # matrix-core plan: no pair words
+    ("u16", (70, 66, 60), 11, 4, 0.3, 2),     # dot2 plan: pair words
+    ("f32", (60, 52, 40), 5, 5, 0.2, 3),
+    ("u16", (40, 40, 40), 5, 3, 1e-6, 4),     # K = 0: statistics only
+])
+def test_combined_call_equals_separate_calls(kind, dims, b, w, frac, seed):
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    p = synth.gen_mri_u16(seed=seed, dims=dims) if kind == "u16" else \
+        synth.gen_random(seed, dims, "f32", smooth=1.0)
+    ref, flt = to_dev(p.ref), to_dev(p.flt)
+    dt = nrr.U16 if kind == "u16" else nrr.F32
+    pairs = kind == "u16" and nrr.match_plan(dt, dims, b, w)["form"] == "dot2"
+    say("select_and_window_stats", kind, dims, b, w, frac)
+    want_c = nrr.select_blocks(ref, b, b, frac).clone()
+    want_ws = nrr.window_stats(flt, b, window=w).clone()
+    for _ in range(2):  # the second call reuses the library's stream and events
+        got_c, got_ws = nrr.select_and_window_stats(ref, flt, b, b, frac, w)
+        torch.cuda.synchronize()
+        assert torch.equal(got_c, want_c)
+        for g, e in zip(defined_bytes(got_ws, dims, b, kind, pairs),
+                        defined_bytes(want_ws, dims, b, kind, pairs)):
+            assert torch.equal(g, e)
+
+
+def test_combined_call_replayed_from_a_graph():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    dims, b, w, frac = (96, 80, 64), 7, 6, 0.25
+    p = synth.gen_mri_u16(seed=5, dims=dims)
+    ref, flt = to_dev(p.ref), to_dev(p.flt)
+    sel_ws = torch.empty(nrr.select_workspace_bytes(dims, b, b), dtype=torch.uint8, device="cuda")
+    mat_ws = torch.empty(nrr.match_workspace_bytes(nrr.U16, dims, b), dtype=torch.uint8,
+                         device="cuda")
+    say("select_and_window_stats under graph capture", dims, b, w)
+    want_c, _ = nrr.select_and_window_stats(ref, flt, b, b, frac, w, sel_ws, mat_ws)
+    want_c = want_c.clone()
+    want_t = defined_bytes(mat_ws, dims, b, "u16", False)[0].clone()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        g_c, _ = nrr.select_and_window_stats(ref, flt, b, b, frac, w, sel_ws, mat_ws)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        mat_ws.fill_(7)  # eager work between the replays
+        g_c.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(g_c, want_c), rep
+        assert torch.equal(defined_bytes(mat_ws, dims, b, "u16", False)[0], want_t), rep
