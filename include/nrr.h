@@ -211,14 +211,17 @@ nrr_status nrr_window_stats(const void *flt, nrr_dtype dtype, const int32_t dims
 /* Selection and window statistics of one step in one call: the plain
  * selection of `ref` (exactly nrr_select_blocks: the same K, centres and
  * errors) and the statistics of `flt` that the search for `window` reads
- * (exactly nrr_window_stats_for), the two running side by side.  The keys
- * kernel goes on `stream`; the statistics go on a second stream of this
- * library (one per device, default priority, created on first use), forked
- * from `stream` after the keys so that the selection's one-workgroup kernel
- * is placed before the statistics fill the device; `stream` waits for both
- * before any later work.  Safe under stream capture (the second stream joins
- * the capture and is joined back).  Concurrent calls on one device are
- * serialised while they enqueue; a call made while another host thread
+ * (exactly nrr_window_stats_for), the two running side by side.  For 12-bit
+ * data, K > 0, grids of at most 32,768 candidates and block edges up to 9,
+ * everything goes on `stream`: the keys, then one launch whose first
+ * workgroup is the selection's radix select and whose other workgroups
+ * compute the statistics (then the plane-pair words if the plan reads
+ * them).  Otherwise the statistics go on a second stream of this library
+ * (one per device, default priority, created on first use), forked from
+ * `stream` after the keys, and `stream` waits for both before any later
+ * work.  Safe under stream capture (a second stream joins the capture and is
+ * joined back).  Concurrent calls on one device are serialised while they
+ * enqueue on the second stream; such a call made while another host thread
  * captures a graph on the same device fails.  Errors as the two calls, plus
  * UNSUPPORTED for device indices of 64 or more. */
 nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dtype dtype,

@@ -15,6 +15,7 @@
 
 #include "nrr.h"
 #include "nrr_internal.h"
+#include "stats_cols.h"
 
 namespace {
 
@@ -505,6 +506,26 @@ nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dty
     note_pairs(match_workspace, pairs);
     const int32_t b3[3] = {block, block, block};
     hipStream_t st = static_cast<hipStream_t>(stream);
+    const nrr::BoxGrid G = nrr::cubic_grid(block, stride, g);
+    const nrr::SelectLayout SL = nrr::select_layout(n);
+    char *sws = static_cast<char *>(select_workspace);
+    uint64_t *keys = k > 0 ? reinterpret_cast<uint64_t *>(sws + SL.keys_off) : nullptr;
+    if (nrr::select_stats_fusable(dtype, n, k, block)) {
+        // one stream: the keys, then the select and the statistics in one
+        // launch (the select's workgroup first), then the plane-pair words
+        // if the plan reads them
+        nrr::launch_keys(ref, dtype, dims, G, n, keys, st);
+        const nrr::StatsLayout L2 = nrr::stats_layout(dtype, dims, b3, pairs);
+        hipError_t e = nrr::launch_select_stats(keys, n, G, k, centers, SL, sws,
+                                                static_cast<const uint16_t *>(flt), dims, block,
+                                                L2, match_workspace, st);
+        if (e == hipSuccess && L2.pair_off)
+            e = nrr::launch_pair_volume(
+                static_cast<const uint16_t *>(flt), dims,
+                reinterpret_cast<uint32_t *>(static_cast<char *>(match_workspace) + L2.pair_off),
+                st);
+        return hip_status(e, "selection and window statistics launch");
+    }
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_status(e, "device query");
@@ -522,10 +543,6 @@ nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dty
     // keys on `stream`; then the statistics on the second stream (forked
     // here, so the selection's one-workgroup kernel, next on `stream`, is
     // placed before the statistics fill the device); `stream` joins them
-    const nrr::BoxGrid G = nrr::cubic_grid(block, stride, g);
-    const nrr::SelectLayout SL = nrr::select_layout(n);
-    char *sws = static_cast<char *>(select_workspace);
-    uint64_t *keys = k > 0 ? reinterpret_cast<uint64_t *>(sws + SL.keys_off) : nullptr;
     if (k > 0) nrr::launch_keys(ref, dtype, dims, G, n, keys, st);
     e = hipEventRecord(fs.fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(fs.side, fs.fork, 0);

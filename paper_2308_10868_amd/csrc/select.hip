@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "nrr_internal.h"
+#include "stats_cols.h"
 
 namespace nrr {
 namespace {
@@ -250,18 +251,28 @@ constexpr int kThrKeys = (int)(kRadixMultiMin / 1024);  // keys per thread
 static_assert(kRadixMultiMin % 1024 == 0, "whole keys per thread");
 constexpr int kThrCopies = 16;  // histogram copies (lane mod 16)
 
-__global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
-                                                           int64_t n, int64_t k,
-                                                           const int64_t *__restrict__ kd,
-                                                           SelectState *__restrict__ st, BoxGrid G,
-                                                           int32_t *__restrict__ centers) {
-    __shared__ __align__(16) uint32_t hist_c[256 * kThrCopies];  // [digit][copy]
-    __shared__ uint32_t hist[256];
-    __shared__ uint64_t list[1024];
-    __shared__ uint64_t s_prefix, s_mask;
-    __shared__ int64_t s_need;
-    __shared__ uint64_t s_or;
-    __shared__ uint32_t s_left, s_count;
+// The select's LDS (a struct, so a fused kernel can overlay it with its other
+// work's LDS).
+struct ThrShared {
+    __align__(16) uint32_t hist_c[256 * kThrCopies];  // [digit][copy]
+    uint32_t hist[256];
+    uint64_t list[1024];
+    uint32_t pre[kThrKeys * 16];  // (above | equal << 16) per (slot, wavefront)
+    uint64_t s_prefix, s_mask, s_or;
+    int64_t s_need;
+    uint32_t s_left, s_count;
+};
+
+// The select of one 1024-thread workgroup (see above).
+__device__ __attribute__((always_inline)) inline void select_threshold_wg(
+    const uint64_t *__restrict__ keys, int64_t n, int64_t k, const int64_t *__restrict__ kd,
+    SelectState *__restrict__ st, const BoxGrid &G, int32_t *__restrict__ centers,
+    ThrShared &sm) {
+    uint32_t *hist_c = sm.hist_c, *hist = sm.hist, *pre = sm.pre;
+    uint64_t *list = sm.list;
+    uint64_t &s_prefix = sm.s_prefix, &s_mask = sm.s_mask, &s_or = sm.s_or;
+    int64_t &s_need = sm.s_need;
+    uint32_t &s_left = sm.s_left, &s_count = sm.s_count;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t kk = kd ? *kd : k;  // K
     if (tid == 0) {
@@ -385,7 +396,6 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
     }
     // ordered compaction: key 1024 j + tid sits in slot j of wavefront w's
     // lane; index order is (slot, wavefront, lane)
-    __shared__ uint32_t pre[kThrKeys * 16];  // (above | equal << 16) per (slot, wavefront)
     const uint64_t kth = s_prefix;
     const int64_t take = s_need;  // equal keys kept, lowest indices first
     uint32_t fgt = 0, feq = 0;  // bit j: key j of this thread is above / equal to the K-th
@@ -451,6 +461,45 @@ __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__res
             centers[3 * pos + 2] = (int32_t)(iz * G.s[2] + (G.b[2] - 1) / 2);
         }
     }
+}
+
+__global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
+                                                           int64_t n, int64_t k,
+                                                           const int64_t *__restrict__ kd,
+                                                           SelectState *__restrict__ st, BoxGrid G,
+                                                           int32_t *__restrict__ centers) {
+    __shared__ ThrShared sm;
+    select_threshold_wg(keys, n, k, kd, st, G, centers, sm);
+}
+
+// The select and the 12-bit column statistics of a cubic block edge B in one
+// launch of 1024-thread workgroups: workgroup 0 is the select (dispatched
+// first, it is placed on a free CU before the statistics fill the device);
+// every other workgroup runs 16 statistics wavefronts (wavefront id = x-tile
+// fastest, then y-tile, then z-run).  No stream fork or join is needed.
+union SelectStatsShared {
+    ThrShared thr;
+    uint2 xch[16][SC_RY][SC_LW];
+};
+
+template <int B>
+__global__ __launch_bounds__(1024) void k_select_stats(
+    const uint64_t *__restrict__ keys, int64_t n, int64_t k, SelectState *__restrict__ st,
+    BoxGrid G, int32_t *__restrict__ centers, const uint16_t *__restrict__ flt, int nx, int ny,
+    int nz, int ox, int oy, int oz, int zc, int nwx, int nwy, int64_t nwaves,
+    StatU16 *__restrict__ out) {
+    __shared__ SelectStatsShared sm;
+    if (blockIdx.x == 0) {
+        select_threshold_wg(keys, n, k, nullptr, st, G, centers, sm.thr);
+        return;
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t wid = (int64_t)(blockIdx.x - 1) * 16 + w;
+    if (wid >= nwaves) return;  // whole wavefront
+    const int xw = (int)(wid % nwx);
+    const int64_t r = wid / nwx;
+    const int yw = (int)(r % nwy), run = (int)(r / nwy);
+    stats_cols_wave<B, B>(flt, nx, ny, nz, B, B, ox, oy, oz, zc, out, xw, yw, run, sm.xch[w]);
 }
 
 // Multi-workgroup radix select for large grids: eight passes of one byte,
@@ -1362,6 +1411,39 @@ void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t
         hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st,
                            G, centers);
     }
+}
+
+bool select_stats_fusable(nrr_dtype dtype, int64_t n, int64_t k, int32_t block) {
+    return dtype == NRR_U16 && k > 0 && n <= kRadixMultiMin && block >= 1 && block <= 9 &&
+           (block & 1);
+}
+
+hipError_t launch_select_stats(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t k,
+                               int32_t *centers, const SelectLayout &SL, char *sws,
+                               const uint16_t *flt, const int32_t dims[3], int32_t block,
+                               const StatsLayout &L, void *stats, hipStream_t stream) {
+    SelectState *st = reinterpret_cast<SelectState *>(sws + SL.state_off);
+    const ColsGrid cg = cols_grid(L, block);
+    const int64_t nwaves = cg.nwx * cg.nwy * cg.runs;
+    const dim3 grid((unsigned)(1 + (nwaves + 15) / 16));
+    StatU16 *out = static_cast<StatU16 *>(stats);
+    switch (block) {
+#define NRR_SELECT_STATS(B)                                                                      \
+    case B:                                                                                      \
+        hipLaunchKernelGGL(k_select_stats<B>, grid, dim3(1024), 0, stream, keys, n, k, st, G,    \
+                           centers, flt, dims[0], dims[1], dims[2], L.ox, L.oy, L.oz, cg.zc,     \
+                           (int)cg.nwx, (int)cg.nwy, nwaves, out);                               \
+        break;
+        NRR_SELECT_STATS(1)
+        NRR_SELECT_STATS(3)
+        NRR_SELECT_STATS(5)
+        NRR_SELECT_STATS(7)
+        NRR_SELECT_STATS(9)
+#undef NRR_SELECT_STATS
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_select(const void *vol, nrr_dtype dtype, const int32_t dims[3],

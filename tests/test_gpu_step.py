@@ -1,6 +1,7 @@
 """GPU: nrr_select_and_window_stats (selection and window statistics side by
-side on two streams) gives exactly what the two separate calls give, eagerly
-and replayed from a captured HIP graph."""
+side: in one launch for 12-bit data and block edges up to 9 on grids the
+one-workgroup select takes, else on two streams) gives exactly what the two
+separate calls give, eagerly and replayed from a captured HIP graph."""
 
 import sys
 
@@ -39,6 +40,7 @@ def defined_bytes(ws, dims, b, dtype, pairs):
     ("u16", (70, 66, 60), 11, 4, 0.3, 2),     # dot2 plan: pair words
     ("f32", (60, 52, 40), 5, 5, 0.2, 3),
     ("u16", (40, 40, 40), 5, 3, 1e-6, 4),     # K = 0: statistics only
+    ("u16", (130, 70, 50), 3, 2, 0.2, 7),     # one launch for both, many statistics workgroups
 ])
 def test_combined_call_equals_separate_calls(kind, dims, b, w, frac, seed):
     import torch
@@ -59,6 +61,28 @@ def test_combined_call_equals_separate_calls(kind, dims, b, w, frac, seed):
         for g, e in zip(defined_bytes(got_ws, dims, b, kind, pairs),
                         defined_bytes(want_ws, dims, b, kind, pairs)):
             assert torch.equal(g, e)
+
+
+def test_combined_call_one_launch_then_pair_words(monkeypatch):
+    """The dot2 form forced for a block edge the one-launch path takes: the
+    pair words follow as a pass of their own."""
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    monkeypatch.setenv("NRR_ARITH", "dot2")
+    dims, b, w, frac = (70, 60, 40), 5, 4, 0.3
+    assert nrr.match_plan(nrr.U16, dims, b, w)["form"] == "dot2"
+    p = synth.gen_mri_u16(seed=6, dims=dims)
+    ref, flt = to_dev(p.ref), to_dev(p.flt)
+    say("select_and_window_stats, dot2 forced", dims, b, w)
+    want_c = nrr.select_blocks(ref, b, b, frac).clone()
+    want_ws = nrr.window_stats(flt, b, window=w).clone()
+    got_c, got_ws = nrr.select_and_window_stats(ref, flt, b, b, frac, w)
+    torch.cuda.synchronize()
+    assert torch.equal(got_c, want_c)
+    for g, e in zip(defined_bytes(got_ws, dims, b, "u16", True),
+                    defined_bytes(want_ws, dims, b, "u16", True)):
+        assert torch.equal(g, e)
 
 
 def test_combined_call_replayed_from_a_graph():
