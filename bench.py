@@ -374,8 +374,10 @@ def main() -> int:
     lat = []
     for _ in range(args.latency_reps):
         t = time.perf_counter()
-        c = nrr.select_blocks(ref, b, stride, frac, workspace=sel_ws)
-        nrr.block_match(ref, flt, c, b, w, workspace=mat_ws, out=(disp, ncc, conf))
+        c, _ = nrr.select_and_window_stats(ref, flt, b, stride, frac, w,
+                                           select_workspace=sel_ws, match_workspace=mat_ws)
+        nrr.block_match(ref, flt, c, b, w, workspace=mat_ws, out=(disp, ncc, conf),
+                        prepared=True)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat)
@@ -416,7 +418,8 @@ def main() -> int:
                    "evaluated_pairs": pairs, "nominal_pairs": nominal, "seed": args.seed},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "reps": args.latency_reps,
-                       "what": "select_blocks + block_match, enqueue to stream sync"},
+                       "what": "select_and_window_stats + block_match(prepared), enqueue "
+                               "to stream sync"},
         "step_launch": "graph (selection + statistics captured once) + search launch"
                        if graph else "eager (faster than the graph replay here)"
                        if graph_step else "eager",
