@@ -6,11 +6,14 @@
 // paper sorts (variance, index) pairs per thread and merges them; here the
 // K-th largest key is found by a radix select over 64-bit keys (no sort of
 // the N candidates is needed) and the chosen blocks are written in ascending
-// grid index by an ordered two-phase compaction.  Ties (equal variance) are
-// broken by the lower grid index, so the result is deterministic.
+// grid index by an ordered compaction (counts, a scan, placement by rank:
+// inside the one-workgroup select on grids of up to 32,768 candidates, two
+// kernels after the multi-workgroup select otherwise).  Ties (equal variance)
+// are broken by the lower grid index, so the result is deterministic.
 //
 // Keys: u16 volumes use the exact integer N*sum(x^2) - (sum x)^2 (= N^2 times
-// the variance, < 2^47 for b <= 15); f32 volumes use the FP64 two-pass
+// the variance, < 2^47 for 12-bit data and b <= 15, < 2^54 for any 16-bit
+// values); f32 volumes use the FP64 two-pass
 // variance summed in z, y, x order without FMA contraction (bit pattern of a
 // non-negative double is monotone in its value).
 #include <hip/hip_runtime.h>
