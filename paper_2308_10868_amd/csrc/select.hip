@@ -1426,7 +1426,13 @@ hipError_t launch_select_stats(const uint64_t *keys, int64_t n, const BoxGrid &G
                                const uint16_t *flt, const int32_t dims[3], int32_t block,
                                const StatsLayout &L, void *stats, hipStream_t stream) {
     SelectState *st = reinterpret_cast<SelectState *>(sws + SL.state_off);
-    const ColsGrid cg = cols_grid(L, block);
+    // one workgroup (16 wavefronts) per CU holds the launch: z-runs cut so
+    // the statistics fill the CUs beside the select's once, not 1.x rounds
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    const ColsGrid cg = cols_grid(L, block, 16 * (int64_t)std::max(ncu - 1, 1));
     const int64_t nwaves = cg.nwx * cg.nwy * cg.runs;
     const dim3 grid((unsigned)(1 + (nwaves + 15) / 16));
     StatU16 *out = static_cast<StatU16 *>(stats);

@@ -156,18 +156,18 @@ __device__ __attribute__((always_inline)) inline void stats_cols_wave(
 }
 
 // Launch shape of the column statistics: x-tiles, y-tiles and z-runs of
-// zc origin planes, runs cut so the launch has about SC_WAVES wavefronts.
+// zc origin planes, runs cut so the launch has about `target` wavefronts.
 struct ColsGrid {
     int64_t nwx, nwy, runs;
     int zc;
 };
 
-inline ColsGrid cols_grid(const StatsLayout &L, int bx) {
+inline ColsGrid cols_grid(const StatsLayout &L, int bx, int64_t target = SC_WAVES) {
     ColsGrid c;
     const int txw = 65 - bx;
     c.nwx = (L.ox + txw - 1) / txw;
     c.nwy = (L.oy + SC_RY - 1) / SC_RY;
-    int64_t runs = (SC_WAVES + c.nwx * c.nwy - 1) / (c.nwx * c.nwy);
+    int64_t runs = (target + c.nwx * c.nwy - 1) / (c.nwx * c.nwy);
     runs = runs < 1 ? 1 : (runs > L.oz ? L.oz : runs);
     c.zc = (int)((L.oz + runs - 1) / runs);
     c.runs = (L.oz + c.zc - 1) / c.zc;
