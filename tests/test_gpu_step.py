@@ -41,6 +41,9 @@ def defined_bytes(ws, dims, b, dtype, pairs):
     ("f32", (60, 52, 40), 5, 5, 0.2, 3),
     ("u16", (40, 40, 40), 5, 3, 1e-6, 4),     # K = 0: statistics only
     ("u16", (130, 70, 50), 3, 2, 0.2, 7),     # one launch for both, many statistics workgroups
+    ("u16", (96, 96, 96), 3, 4, 0.37, 8),     # 32,768 candidates: the most the one launch takes
+    ("u16", (12, 9, 8), 3, 2, 0.5, 9),        # one statistics wavefront, a ragged select
+    ("u16", (80, 70, 60), 9, 5, 0.25, 10),    # the largest edge of the one launch
 ])
 def test_combined_call_equals_separate_calls(kind, dims, b, w, frac, seed):
     import torch
