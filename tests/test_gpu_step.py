@@ -66,6 +66,24 @@ def test_combined_call_equals_separate_calls(kind, dims, b, w, frac, seed):
             assert torch.equal(g, e)
 
 
+def test_combined_call_against_the_oracle_and_box_sums():
+    """The one-launch path checked directly: centres against oracle.select,
+    the table's records against box sums of flt computed here."""
+    import torch
+    import oracle
+    from tests.test_gpu_stats_table import check_u16_records
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    dims, b, w, frac = (120, 100, 70), 7, 6, 0.25
+    p = synth.gen_mri_u16(seed=12, dims=dims)
+    say("select_and_window_stats against the oracle", dims, b, w, frac)
+    c, ws = nrr.select_and_window_stats(to_dev(p.ref), to_dev(p.flt), b, b, frac, w)
+    torch.cuda.synchronize()
+    exp, _ = oracle.select(p.ref, b, b, frac)
+    assert np.array_equal(c.cpu().numpy(), exp)
+    check_u16_records(ws.cpu().numpy(), p.flt, (b, b, b))
+
+
 def test_combined_call_one_launch_then_pair_words(monkeypatch):
     """The dot2 form forced for a block edge the one-launch path takes: the
     pair words follow as a pass of their own."""
