@@ -296,3 +296,28 @@ def test_select_count_aniso_matches_the_rule():
         assert list(g) == grid and kk.value == k
     with pytest.raises(nrr.NrrError):
         nrr.select_count_aniso((10, 10, 10), (4, 3, 3), (1, 1, 1), 0.5)  # even edge
+
+
+def test_select_and_window_stats_validation(lib):
+    """nrr_select_and_window_stats checks its arguments before any launch:
+    K is reported even when the call fails on capacity."""
+    d = (ctypes.c_int32 * 3)(64, 64, 64)
+    k = ctypes.c_int64(-1)
+    P = ctypes.c_void_p
+    call = lambda **kw: lib.nrr_select_and_window_stats(
+        kw.get("ref", P(1)), kw.get("flt", P(1)), kw.get("dtype", 0), d, kw.get("block", 7),
+        kw.get("stride", 7), kw.get("fraction", 0.2), kw.get("window", 3),
+        kw.get("centers", P(1)), kw.get("capacity", 1000), kw.get("k_out", ctypes.byref(k)),
+        kw.get("sws", P(1)), kw.get("sbytes", 1 << 30), kw.get("mws", P(1)),
+        kw.get("mbytes", 1 << 30), None)
+    assert call(k_out=None) == 1
+    assert call(fraction=0.0) == 1 and call(fraction=1.5) == 1
+    assert call(window=-1) == 1
+    assert call(block=8) == 1            # even edge
+    assert call(block=17) == 4           # not built
+    assert call(dtype=7) == 1
+    assert call(ref=None) == 1 and call(mws=None) == 1
+    assert call(capacity=10) == 2        # K = floor(0.5 + 729 * 0.2) = 146
+    assert k.value == 146
+    assert call(sbytes=16) == 2 and b"selection workspace" in lib.nrr_last_error()
+    assert call(mbytes=16) == 2 and b"match workspace" in lib.nrr_last_error()
