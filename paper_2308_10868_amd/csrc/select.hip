@@ -1147,11 +1147,15 @@ __device__ inline uint64_t key_f32_seq(const float *v, int nb) {
 
 // One wavefront per candidate: the wavefront copies the block to LDS, then
 // its first lane sums it in the fixed order (the result does not depend on
-// how the block was fetched).  Grid: (candidates / 4, sets).
+// how the block was fetched).  The staging holds blocks of edge 9 at most,
+// the largest edge batched plans are built for (the batched variant table
+// has edges 5, 7 and 9; plans with others are refused): 12 KB per workgroup,
+// so many workgroups share a CU, as the sums are one lane's dependent FP64
+// chain.  Grid: (candidates / 4, sets).
 __global__ __launch_bounds__(256) void k_batch_keys(const void *__restrict__ vol, int is_u16,
                                                     int nx, int ny,
                                                     const BatchSelectSet *__restrict__ sets) {
-    constexpr int MAXV = 15 * 15 * 15;
+    constexpr int MAXV = 9 * 9 * 9;
     __shared__ float blk[4][MAXV];
     const BatchSelectSet &S = sets[blockIdx.y];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1161,6 +1165,7 @@ __global__ __launch_bounds__(256) void k_batch_keys(const void *__restrict__ vol
     const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
     const int64_t x0 = (int64_t)ix * S.stride, y0 = (int64_t)iy * S.stride,
                   z0 = (int64_t)iz * S.stride;
+
     for (int o = lane; o < nb; o += 64) {
         const int z = o / (b * b), y = (o / b) % b, x = o % b;
         const int64_t at = ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0 + x;
