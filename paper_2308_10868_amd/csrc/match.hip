@@ -872,13 +872,6 @@ __global__ __launch_bounds__(NT) void k_match_surf(Params p) {
     X(4, 7, 3, 3, 0) X(5, 9, 3, 3, 0)
 #define BATCH_U16(X) X(0, 5, 4, 4, 0) X(1, 7, 3, 7, 1) X(2, 7, 4, 4, 0) X(3, 9, 4, 4, 0) \
     X(4, 9, 5, 5, 0) X(5, 5, 3, 3, 0)
-// The batched selection keys stage one block per wavefront in LDS sized for
-// an edge of 9; a batched shape with a larger edge needs that staging grown.
-#define BATCH_EDGE_OK(i, b, rx, ry, f) \
-    static_assert((b) <= 9, "batched key staging holds blocks of edge 9 at most");
-BATCH_F32(BATCH_EDGE_OK)
-BATCH_U16(BATCH_EDGE_OK)
-#undef BATCH_EDGE_OK
 
 template <typename Vox>
 __global__ __launch_bounds__(256) void k_match_batch(const BatchSet *__restrict__ sets, int nsets,

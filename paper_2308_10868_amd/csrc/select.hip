@@ -180,35 +180,82 @@ __global__ __launch_bounds__(256) void k_block_keys_u16_tiled(const uint16_t *__
     }
 }
 
+// Calls f on every voxel of the bx*by*bz block at base, in z, y, x order.
+// A row of up to R voxels is loaded from one address (immediate offsets, no
+// per-voxel address arithmetic), and the next row's loads are issued before
+// the current row reaches f, so a chain of dependent additions in f overlaps
+// the next memory round trip.  Longer rows take plain loops.
+template <typename F>
+__device__ inline void block_in_order(const float *__restrict__ base, int64_t nx, int64_t plane,
+                                      int bx, int by, int bz, F &&f) {
+    constexpr int R = 16;
+    const int rows = by * bz;
+    if (bx > R) {
+        for (int r = 0; r < rows; ++r) {
+            const float *p = base + (int64_t)(r / by) * plane + (int64_t)(r % by) * nx;
+            for (int x = 0; x < bx; ++x) f(p[x]);
+        }
+        return;
+    }
+    const float *p = base;  // the next row to load
+    int y = 0;
+    auto advance = [&]() {
+        if (++y == by) {
+            y = 0;
+            p += plane - (int64_t)(by - 1) * nx;
+        } else {
+            p += nx;
+        }
+    };
+    auto load = [&](float(&t)[R]) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (j < bx) t[j] = p[j];
+        advance();
+    };
+    auto use = [&](const float(&t)[R]) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if (j < bx) f(t[j]);
+    };
+    float ta[R], tb[R];
+    load(ta);
+    int r = 0;
+    for (; r + 2 <= rows; r += 2) {
+        load(tb);  // row r + 1
+        use(ta);
+        if (r + 2 < rows) load(ta);  // row r + 2
+        use(tb);
+    }
+    if (r < rows) use(ta);
+}
+
 // FP64 two-pass variance of the bx*by*bz block at (x0, y0, z0), summed in
 // z, y, x order without contraction; returned as its (monotone) bit pattern.
 __device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int bx, int by,
                                    int bz, int64_t x0, int64_t y0, int64_t z0) {
 #pragma clang fp contract(off)
-    double nb = (double)bx * by * bz;
+    const float *base = vol + (z0 * ny + y0) * (int64_t)nx + x0;
+    const int64_t plane = (int64_t)ny * nx;
+    const double dn = (double)bx * by * bz;
     double sum = 0.0;
-    for (int z = 0; z < bz; ++z)
-        for (int y = 0; y < by; ++y) {
-            const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            for (int x = 0; x < bx; ++x) sum += (double)row[x];
-        }
-    double mean = sum / nb;
+    block_in_order(base, nx, plane, bx, by, bz, [&](float v) { sum += (double)v; });
+    const double mean = sum / dn;
     double ss = 0.0;
-    for (int z = 0; z < bz; ++z)
-        for (int y = 0; y < by; ++y) {
-            const float *row = vol + ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0;
-            for (int x = 0; x < bx; ++x) {
-                double d = (double)row[x] - mean;
-                ss += d * d;
-            }
-        }
-    double var = ss / nb;
+    block_in_order(base, nx, plane, bx, by, bz, [&](float v) {
+        const double d = (double)v - mean;
+        ss += d * d;
+    });
+    const double var = ss / dn;
     return (uint64_t)__double_as_longlong(var);  // var >= +0: bit pattern is monotone
 }
 
-__global__ __launch_bounds__(256) void k_block_keys_f32(const float *__restrict__ vol, int nx,
-                                                        int ny, BoxGrid G, int64_t n,
-                                                        uint64_t *__restrict__ keys) {
+// Float keys, one thread per candidate.  64-thread workgroups spread a small
+// grid's candidates over many CUs: a wavefront's loads reach one cache line
+// per few lanes, so each CU's vector memory path is the bound.
+__global__ __launch_bounds__(64) void k_block_keys_f32(const float *__restrict__ vol, int nx,
+                                                       int ny, BoxGrid G, int64_t n,
+                                                       uint64_t *__restrict__ keys) {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const int gi = (int)g, gxy = G.g[0] * G.g[1];
@@ -1125,69 +1172,54 @@ __global__ void k_ex_want(double fraction, int64_t *__restrict__ ctr, int64_t *_
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Batched selection for small candidate grids.  The keys of every set's
-// candidates are computed first (one thread per candidate, grid y = set);
-// then one workgroup per set sorts (key descending, grid index ascending)
-// with a bitonic network in LDS, keeps the first K and writes their centres
-// in ascending grid index.  Same keys and tie rule as the radix-select path,
-// so the same blocks come out.
-// FP64 two-pass variance of nb values in order (the order of key_f32).
-__device__ inline uint64_t key_f32_seq(const float *v, int nb) {
-#pragma clang fp contract(off)
-    const double dn = (double)nb;
-    double sum = 0.0;
-    for (int o = 0; o < nb; ++o) sum += (double)v[o];
-    const double mean = sum / dn;
-    double ss = 0.0;
-    for (int o = 0; o < nb; ++o) {
-        const double d = (double)v[o] - mean;
-        ss += d * d;
-    }
-    return (uint64_t)__double_as_longlong(ss / dn);
-}
+// candidates are computed first (grid y = set); then one workgroup per set
+// sorts (key descending, grid index ascending) with a bitonic network in LDS,
+// keeps the first K and writes their centres in ascending grid index.  Same
+// keys and tie rule as the radix-select path, so the same blocks come out.
 
-// One wavefront per candidate: the wavefront copies the block to LDS, then
-// its first lane sums it in the fixed order (the result does not depend on
-// how the block was fetched).  The staging holds blocks of edge 9 at most,
-// the largest edge batched plans are built for (the batched variant table
-// has edges 5, 7 and 9; plans with others are refused): 12 KB per workgroup,
-// so many workgroups share a CU, as the sums are one lane's dependent FP64
-// chain.  Grid: (candidates / 4, sets).
-__global__ __launch_bounds__(256) void k_batch_keys(const void *__restrict__ vol, int is_u16,
-                                                    int nx, int ny,
-                                                    const BatchSelectSet *__restrict__ sets) {
-    constexpr int MAXV = 9 * 9 * 9;
-    __shared__ float blk[4][MAXV];
+// Batched selection keys, 12-bit data: one wavefront per candidate; the sums
+// are exact integers, so every lane adds the voxels it loads and the
+// wavefront reduces them.  Grid: (candidates / 4, sets).
+__global__ __launch_bounds__(256) void k_batch_keys_u16(const uint16_t *__restrict__ vol, int nx,
+                                                        int ny,
+                                                        const BatchSelectSet *__restrict__ sets) {
     const BatchSelectSet &S = sets[blockIdx.y];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + wv;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= S.ncand) return;  // whole wavefront leaves together
     const int b = S.b, nb = b * b * b;
     const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
     const int64_t x0 = (int64_t)ix * S.stride, y0 = (int64_t)iy * S.stride,
                   z0 = (int64_t)iz * S.stride;
-
+    uint64_t s = 0, q = 0;
     for (int o = lane; o < nb; o += 64) {
         const int z = o / (b * b), y = (o / b) % b, x = o % b;
-        const int64_t at = ((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0 + x;
-        blk[wv][o] = is_u16 ? (float)static_cast<const uint16_t *>(vol)[at]
-                            : static_cast<const float *>(vol)[at];
+        const uint64_t v = vol[((z0 + z) * ny + (y0 + y)) * (int64_t)nx + x0 + x];
+        s += v;
+        q += v * v;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane != 0) return;
-    const float *v = blk[wv];
-    if (is_u16) {  // exact integers (12-bit values are exact in float)
-        uint64_t s = 0, q = 0;
-        for (int o = 0; o < nb; ++o) {
-            const uint64_t x = (uint64_t)v[o];
-            s += x;
-            q += x * x;
-        }
-        S.keys[i] = (uint64_t)nb * q - s * s;
-        return;
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        q += __shfl_xor(q, off);
     }
-    S.keys[i] = key_f32_seq(v, nb);
+    if (lane == 0) S.keys[i] = (uint64_t)nb * q - s * s;
+}
+
+// Batched selection keys, float data: one thread per candidate, key_f32 in
+// the plain selection's order (so a set's keys equal a plain call's).  Each
+// lane's sums are a dependent FP64 chain of its own, so all 64 lanes work;
+// neighbouring lanes read neighbouring blocks, a few lanes to a cache line.
+// 64-thread workgroups spread a set's few candidates over many CUs, whose
+// vector memory paths bound these loads.  Grid: (candidates / 64, sets).
+__global__ __launch_bounds__(64) void k_batch_keys_f32(const float *__restrict__ vol, int nx,
+                                                       int ny,
+                                                       const BatchSelectSet *__restrict__ sets) {
+    const BatchSelectSet &S = sets[blockIdx.y];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= S.ncand) return;
+    const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
+    S.keys[i] = key_f32(vol, nx, ny, S.b, S.b, S.b, (int64_t)ix * S.stride,
+                        (int64_t)iy * S.stride, (int64_t)iz * S.stride);
 }
 
 __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__restrict__ sets) {
@@ -1254,9 +1286,13 @@ __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__r
 hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                const BatchSelectSet *sets, int nsets, int64_t max_cand,
                                hipStream_t stream) {
-    if (max_cand > 0)
-        hipLaunchKernelGGL(k_batch_keys, dim3((unsigned)((max_cand + 3) / 4), (unsigned)nsets),
-                           dim3(256), 0, stream, vol, dtype == NRR_U16 ? 1 : 0, dims[0], dims[1],
+    if (max_cand > 0 && dtype == NRR_U16)
+        hipLaunchKernelGGL(k_batch_keys_u16, dim3((unsigned)((max_cand + 3) / 4), (unsigned)nsets),
+                           dim3(256), 0, stream, static_cast<const uint16_t *>(vol), dims[0],
+                           dims[1], sets);
+    else if (max_cand > 0)
+        hipLaunchKernelGGL(k_batch_keys_f32, dim3((unsigned)((max_cand + 63) / 64), (unsigned)nsets),
+                           dim3(64), 0, stream, static_cast<const float *>(vol), dims[0], dims[1],
                            sets);
     hipLaunchKernelGGL(k_select_batch, dim3((unsigned)nsets), dim3(1024), 0, stream, sets);
     return hipGetLastError();
@@ -1357,8 +1393,8 @@ void launch_keys(const void *vol, nrr_dtype dtype, const int32_t dims[3], const 
         hipLaunchKernelGGL(k_block_keys_u16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream,
                            static_cast<const uint16_t *>(vol), dims[0], dims[1], G, n, keys);
     else
-        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           stream, static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
+        hipLaunchKernelGGL(k_block_keys_f32, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, stream,
+                           static_cast<const float *>(vol), dims[0], dims[1], G, n, keys);
 }
 
 SelectLayout select_layout(int64_t n_candidates, bool variants) {

@@ -97,3 +97,29 @@ def test_float_select_one_workgroup(torch_dev):
     got = gpu_select(vol, 5, 5, 0.2)
     exp, _ = oracle.select(vol, 5, 5, 0.2)
     assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("dims,b,stride,wide", [
+    ((40, 33, 21), 3, 1, False),   # 27 voxels: one partial load batch
+    ((31, 29, 23), 5, 2, True),    # 125: full batches and a partial one
+    ((40, 36, 30), 9, 3, True),    # 729: many batches
+    ((17, 17, 16), 15, 1, True),   # 3375: the largest edge
+])
+def test_float_keys_bitwise_against_the_oracle(torch_dev, dims, b, stride, wide):
+    """Every candidate's float key (the FP64 two-pass variance summed in z, y,
+    x order, left by the plain selection at the start of its workspace) equals
+    the oracle's bit for bit.  With values spread over many binades a sum
+    taken in another order would round differently."""
+    torch = torch_dev
+    say("float keys", dims, b, stride, wide)
+    vol = synth.gen_random(b + stride, dims, "f32", smooth=0.0 if wide else 0.8).ref
+    if wide:
+        rng = np.random.default_rng(b * 7 + stride)
+        vol = (vol * 10.0 ** rng.uniform(-4, 4, size=vol.shape)).astype(np.float32)
+    ws = torch.zeros(nrr.select_workspace_bytes(dims, b, stride), dtype=torch.uint8,
+                     device="cuda")
+    nrr.select_blocks(to_dev(vol), b, stride, 0.3, workspace=ws)
+    torch.cuda.synchronize()
+    key, _ = oracle.block_variance(vol, b, stride)
+    got = ws[:key.size * 8].view(torch.int64).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, key.view(np.uint64))
