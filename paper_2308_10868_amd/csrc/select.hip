@@ -180,74 +180,107 @@ __global__ __launch_bounds__(256) void k_block_keys_u16_tiled(const uint16_t *__
     }
 }
 
-// Calls f on every voxel of the bx*by*bz block at base, in z, y, x order.
-// A row of up to R voxels is loaded from one address (immediate offsets, no
-// per-voxel address arithmetic), and the next row's loads are issued before
-// the current row reaches f, so a chain of dependent additions in f overlaps
-// the next memory round trip.  Longer rows take plain loops.
-template <typename F>
-__device__ inline void block_in_order(const float *__restrict__ base, int64_t nx, int64_t plane,
-                                      int bx, int by, int bz, F &&f) {
-    constexpr int R = 16;
+// Calls f on every voxel of the BX*by*bz block at base, in z, y, x order.
+// A row is BX loads from one address (immediate offsets, straight-line code,
+// so the compiler's waits count exactly the loads still needed), and the
+// loads of the next three rows are in flight while a row reaches f: a chain
+// of dependent additions in f overlaps the memory round trips.  Loads past
+// the last row repeat the last row (in bounds, never passed to f).
+template <int BX, typename F>
+__device__ __forceinline__ void block_rows_in_order(const float *__restrict__ base, int64_t nx,
+                                                    int64_t plane, int by, int bz, F &&f) {
     const int rows = by * bz;
-    if (bx > R) {
-        for (int r = 0; r < rows; ++r) {
-            const float *p = base + (int64_t)(r / by) * plane + (int64_t)(r % by) * nx;
-            for (int x = 0; x < bx; ++x) f(p[x]);
-        }
-        return;
-    }
     const float *p = base;  // the next row to load
-    int y = 0;
-    auto advance = [&]() {
-        if (++y == by) {
-            y = 0;
-            p += plane - (int64_t)(by - 1) * nx;
-        } else {
-            p += nx;
+    int y = 0, left = rows - 1;  // rows after the one p points at
+    auto load = [&](float(&t)[BX]) {
+#pragma unroll
+        for (int j = 0; j < BX; ++j) t[j] = p[j];
+        if (left > 0) {
+            --left;
+            if (++y == by) {
+                y = 0;
+                p += plane - (int64_t)(by - 1) * nx;
+            } else {
+                p += nx;
+            }
         }
     };
-    auto load = [&](float(&t)[R]) {
+    auto use = [&](const float(&t)[BX]) {
 #pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (j < bx) t[j] = p[j];
-        advance();
+        for (int j = 0; j < BX; ++j) f(t[j]);
     };
-    auto use = [&](const float(&t)[R]) {
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-            if (j < bx) f(t[j]);
-    };
-    float ta[R], tb[R];
-    load(ta);
-    int r = 0;
-    for (; r + 2 <= rows; r += 2) {
-        load(tb);  // row r + 1
-        use(ta);
-        if (r + 2 < rows) load(ta);  // row r + 2
-        use(tb);
+    float t0[BX], t1[BX], t2[BX], t3[BX];  // a ring: row r in t[r % 4]
+    load(t0);
+    load(t1);
+    load(t2);
+    for (int r = 0; r < rows; r += 4) {
+        load(t3);
+        use(t0);
+        load(t0);
+        if (r + 1 < rows) use(t1);
+        load(t1);
+        if (r + 2 < rows) use(t2);
+        load(t2);
+        if (r + 3 < rows) use(t3);
     }
-    if (r < rows) use(ta);
+}
+
+// FP64 two-pass variance of the BX*by*bz block at base, summed in z, y, x
+// order without contraction; returned as its (monotone) bit pattern.
+template <int BX>
+__device__ __forceinline__ uint64_t key_f32_rows(const float *__restrict__ base, int64_t nx,
+                                                 int64_t plane, int by, int bz) {
+#pragma clang fp contract(off)
+    const double dn = (double)BX * by * bz;
+    double sum = 0.0;
+    block_rows_in_order<BX>(base, nx, plane, by, bz, [&](float v) { sum += (double)v; });
+    const double mean = sum / dn;
+    double ss = 0.0;
+    block_rows_in_order<BX>(base, nx, plane, by, bz, [&](float v) {
+        const double d = (double)v - mean;
+        ss += d * d;
+    });
+    return (uint64_t)__double_as_longlong(ss / dn);
 }
 
 // FP64 two-pass variance of the bx*by*bz block at (x0, y0, z0), summed in
 // z, y, x order without contraction; returned as its (monotone) bit pattern.
-__device__ inline uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int bx, int by,
-                                   int bz, int64_t x0, int64_t y0, int64_t z0) {
+// Odd row lengths up to 15 take the prefetching row walk, others plain loops
+// (the same order, so the same result).
+__device__ __forceinline__ uint64_t key_f32(const float *__restrict__ vol, int nx, int ny, int bx,
+                                            int by, int bz, int64_t x0, int64_t y0,
+                                            int64_t z0) {
 #pragma clang fp contract(off)
     const float *base = vol + (z0 * ny + y0) * (int64_t)nx + x0;
     const int64_t plane = (int64_t)ny * nx;
+    switch (bx) {
+    case 3: return key_f32_rows<3>(base, nx, plane, by, bz);
+    case 5: return key_f32_rows<5>(base, nx, plane, by, bz);
+    case 7: return key_f32_rows<7>(base, nx, plane, by, bz);
+    case 9: return key_f32_rows<9>(base, nx, plane, by, bz);
+    case 11: return key_f32_rows<11>(base, nx, plane, by, bz);
+    case 13: return key_f32_rows<13>(base, nx, plane, by, bz);
+    case 15: return key_f32_rows<15>(base, nx, plane, by, bz);
+    default: break;
+    }
     const double dn = (double)bx * by * bz;
     double sum = 0.0;
-    block_in_order(base, nx, plane, bx, by, bz, [&](float v) { sum += (double)v; });
+    for (int z = 0; z < bz; ++z)
+        for (int y = 0; y < by; ++y) {
+            const float *row = base + (int64_t)z * plane + (int64_t)y * nx;
+            for (int x = 0; x < bx; ++x) sum += (double)row[x];
+        }
     const double mean = sum / dn;
     double ss = 0.0;
-    block_in_order(base, nx, plane, bx, by, bz, [&](float v) {
-        const double d = (double)v - mean;
-        ss += d * d;
-    });
-    const double var = ss / dn;
-    return (uint64_t)__double_as_longlong(var);  // var >= +0: bit pattern is monotone
+    for (int z = 0; z < bz; ++z)
+        for (int y = 0; y < by; ++y) {
+            const float *row = base + (int64_t)z * plane + (int64_t)y * nx;
+            for (int x = 0; x < bx; ++x) {
+                const double d = (double)row[x] - mean;
+                ss += d * d;
+            }
+        }
+    return (uint64_t)__double_as_longlong(ss / dn);  // var >= +0: bit pattern is monotone
 }
 
 // Float keys, one thread per candidate.  64-thread workgroups spread a small
