@@ -325,7 +325,8 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
 // highest set bit of all keys; the last one may overlap bits already fixed
 // (those are equal in every key it counts, so the pick is unchanged).
 // K comes from `k`, or from *kd when kd is given (a count made on the device);
-// K = 0 selects nothing.
+// K = 0 selects nothing.  The K-th key and the equal keys kept go to *st when
+// st is given.
 // The same workgroup then writes the chosen blocks' centres in ascending grid
 // index (the ordered compaction, from the registers): per key slot and
 // wavefront it counts the keys above and equal to the K-th by ballots, scans
@@ -473,7 +474,7 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
             n_list = min(s_count, 1024u);
         }
     }
-    if (tid == 0) {
+    if (tid == 0 && st) {
         st->kth = s_prefix;
         st->take_eq = s_need;
     }
@@ -1206,9 +1207,8 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Batched selection for small candidate grids.  The keys of every set's
 // candidates are computed first (grid y = set); then one workgroup per set
-// sorts (key descending, grid index ascending) with a bitonic network in LDS,
-// keeps the first K and writes their centres in ascending grid index.  Same
-// keys and tie rule as the radix-select path, so the same blocks come out.
+// selects and writes the centres in ascending grid index.  The keys, the tie
+// rule and the select are the plain path's, so the same blocks come out.
 
 // Batched selection keys, 12-bit data: one wavefront per candidate; the sums
 // are exact integers, so every lane adds the voxels it loads and the
@@ -1255,63 +1255,20 @@ __global__ __launch_bounds__(64) void k_batch_keys_f32(const float *__restrict__
                         (int64_t)iy * S.stride, (int64_t)iz * S.stride);
 }
 
+// Per set, the plain path's one-workgroup select (radix passes for the K-th
+// key, then the ordered compaction), so a set's centres are a plain call's.
 __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__restrict__ sets) {
-    __shared__ uint64_t key[kBatchCand];
-    __shared__ uint16_t idx[kBatchCand];
-    __shared__ uint8_t sel[kBatchCand];
-    __shared__ int wsum[16];
-    const BatchSelectSet S = sets[blockIdx.x];
-    const int tid = threadIdx.x, n = (int)S.ncand;
-    int n2 = 1;
-    while (n2 < n) n2 <<= 1;
-    for (int i = tid; i < n2; i += 1024) {
-        key[i] = i < n ? S.keys[i] : 0;  // padding sorts after every candidate (largest index)
-        idx[i] = (uint16_t)(i < n ? i : 0xffff);
-        if (i < n) sel[i] = 0;
+    __shared__ ThrShared sm;
+    const BatchSelectSet &S = sets[blockIdx.x];
+    BoxGrid G;
+    for (int a = 0; a < 3; ++a) {
+        G.b[a] = S.b;
+        G.s[a] = S.stride;
     }
-    __syncthreads();
-    auto before = [&](int a, int c) {  // a ranks before c
-        return key[a] > key[c] || (key[a] == key[c] && idx[a] < idx[c]);
-    };
-    for (int k = 2; k <= n2; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = tid; i < n2; i += 1024) {
-                const int l = i ^ j;
-                if (l > i && (((i & k) == 0) ? before(l, i) : before(i, l))) {
-                    const uint64_t tk = key[i];
-                    key[i] = key[l];
-                    key[l] = tk;
-                    const uint16_t ti = idx[i];
-                    idx[i] = idx[l];
-                    idx[l] = ti;
-                }
-            }
-            __syncthreads();
-        }
-    for (int i = tid; i < S.k; i += 1024) sel[idx[i]] = 1;
-    __syncthreads();
-    // ordered compaction: each thread owns a run of consecutive candidates
-    const int per = (n + 1023) / 1024, lo = min(n, tid * per), hi = min(n, lo + per);
-    int cnt = 0;
-    for (int i = lo; i < hi; ++i) cnt += sel[i];
-    int incl = cnt;  // inclusive scan over the wavefront, then over wavefronts
-    for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off);
-        if ((tid & 63) >= off) incl += o;
-    }
-    if ((tid & 63) == 63) wsum[tid >> 6] = incl;
-    __syncthreads();
-    int pos = incl - cnt;
-    for (int w = 0; w < (tid >> 6); ++w) pos += wsum[w];
-    const int h = (S.b - 1) / 2;
-    for (int i = lo; i < hi; ++i)
-        if (sel[i]) {
-            const int ix = i % S.gx, iy = (i / S.gx) % S.gy, iz = i / (S.gx * S.gy);
-            S.centers[3 * pos] = ix * S.stride + h;
-            S.centers[3 * pos + 1] = iy * S.stride + h;
-            S.centers[3 * pos + 2] = iz * S.stride + h;
-            ++pos;
-        }
+    G.g[0] = S.gx;
+    G.g[1] = S.gy;
+    G.g[2] = S.gz;
+    select_threshold_wg(S.keys, S.ncand, S.k, nullptr, nullptr, G, S.centers, sm);
 }
 
 }  // namespace
