@@ -1009,10 +1009,19 @@ namespace {
 // The launches of one batch on `st`: window statistics per block size, the
 // batched selection, the persistent search.
 hipError_t batch_enqueue(const nrr_batch_plan &P, hipStream_t st) {
-    for (size_t i = 0; i < P.L.bvals.size(); ++i) {
-        hipError_t e = nrr::launch_stats(P.flt, P.dtype, P.dims, P.L.bvals[i],
-                                         P.ws + P.L.stats_off[i], st);
+    const size_t nb = P.L.bvals.size();
+    if (P.dtype == NRR_F32 && nb >= 1 && nb <= (size_t)nrr::kStatsJobs) {
+        void *outs[nrr::kStatsJobs];
+        for (size_t i = 0; i < nb; ++i) outs[i] = P.ws + P.L.stats_off[i];
+        hipError_t e = nrr::launch_stats_f32_multi(static_cast<const float *>(P.flt), P.dims,
+                                                   P.L.bvals.data(), outs, (int)nb, st);
         if (e != hipSuccess) return e;
+    } else {
+        for (size_t i = 0; i < nb; ++i) {
+            hipError_t e = nrr::launch_stats(P.flt, P.dtype, P.dims, P.L.bvals[i],
+                                             P.ws + P.L.stats_off[i], st);
+            if (e != hipSuccess) return e;
+        }
     }
     if (P.nsets == 0) return hipSuccess;
     hipError_t e = nrr::launch_select_batch(

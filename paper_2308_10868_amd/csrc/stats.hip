@@ -64,11 +64,11 @@ __device__ inline void lds_barrier() {
 template <typename V, typename A, typename AQ, typename AS, typename AQQ, typename Src,
           typename Conv, typename Emit>
 __device__ inline void stats_body(const Src *__restrict__ flt, int nx, int ny, int nz, int bx,
-                                  int by, int bz, int ox, int oy, int oz, int zc,
-                                  V *patch /*[2][PATCH]*/, A *rs, AQ *rq, A *ringP, AQ *ringQ,
-                                  Conv conv, Emit emit) {
+                                  int by, int bz, int ox, int oy, int oz, int zc, int tile_x,
+                                  int tile_y, int run, V *patch /*[2][PATCH]*/, A *rs, AQ *rq,
+                                  A *ringP, AQ *ringQ, Conv conv, Emit emit) {
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;  // output (tx, ty)
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * zc;
+    const int x0 = tile_x * TX, y0 = tile_y * TY, z0 = run * zc;
     const int ph = TY + by - 1, pw = TX + bx - 1;
     const int zend = min(z0 + zc + bz - 1, nz);  // input planes [z0, zend)
     // this thread's patch elements: fixed offsets inside a plane
@@ -195,8 +195,50 @@ __global__ __launch_bounds__(256) void k_stats_f32(const float *__restrict__ flt
     double *ringQ = reinterpret_cast<double *>(dyn_f32 + (size_t)bz * 256 * 8);
     const double n = (double)bx * by * bz;
     stats_body<float, double, double, double, double>(
-        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, patch, rs, rq, ringP, ringQ,
-        [](float v) { return v; },
+        flt, nx, ny, nz, bx, by, bz, ox, oy, oz, zc, blockIdx.x, blockIdx.y, blockIdx.z, patch, rs,
+        rq, ringP, ringQ, [](float v) { return v; },
+        [&](int64_t o, double S, double QQ) {
+            const double nq = n * QQ;
+            const double var = nq - S * S;
+            StatF32 rec;
+            rec.s = S;
+            rec.r = var > 1e-12 * nq ? 1.0 / sqrt(var) : 0.0;
+            out[o] = rec;
+        });
+}
+
+// One cubic block edge's share of a several-edge float statistics launch.
+struct StatsF32Job {
+    int b, ox, oy, oz, zc;
+    int tiles_x, tiles_y, z_first;  // its tiles, and its first grid z (its runs follow)
+    StatF32 *out;
+};
+struct StatsF32Jobs {
+    StatsF32Job job[kStatsJobs];
+    int n;
+};
+
+// Float statistics of several block edges over one volume in one launch:
+// grid z holds each edge's runs in turn, and a workgroup past its edge's x
+// or y tiles leaves at once.  The same body and records as k_stats_f32.
+__global__ __launch_bounds__(256) void k_stats_f32_multi(const float *__restrict__ flt, int nx,
+                                                         int ny, int nz, StatsF32Jobs J) {
+    __shared__ float patch[2 * PATCH + 256];
+    __shared__ double rs[PH * TX];
+    __shared__ double rq[PH * TX];
+    extern __shared__ __align__(16) unsigned char dyn_f32m[];
+    StatsF32Job jb = J.job[0];
+#pragma unroll
+    for (int i = 1; i < kStatsJobs; ++i)  // constant indices: the table stays in kernel arguments
+        if (i < J.n && (int)blockIdx.z >= J.job[i].z_first) jb = J.job[i];
+    if ((int)blockIdx.x >= jb.tiles_x || (int)blockIdx.y >= jb.tiles_y) return;
+    double *ringP = reinterpret_cast<double *>(dyn_f32m);
+    double *ringQ = reinterpret_cast<double *>(dyn_f32m + (size_t)jb.b * 256 * 8);
+    const double n = (double)jb.b * jb.b * jb.b;
+    StatF32 *out = jb.out;
+    stats_body<float, double, double, double, double>(
+        flt, nx, ny, nz, jb.b, jb.b, jb.b, jb.ox, jb.oy, jb.oz, jb.zc, blockIdx.x, blockIdx.y,
+        (int)blockIdx.z - jb.z_first, patch, rs, rq, ringP, ringQ, [](float v) { return v; },
         [&](int64_t o, double S, double QQ) {
             const double nq = n * QQ;
             const double var = nq - S * S;
@@ -332,6 +374,22 @@ StatsLayout stats_layout(nrr_dtype dtype, const int32_t dims[3], int32_t block) 
     return stats_layout(dtype, dims, b3, true);
 }
 
+namespace {
+// Origin planes per float statistics workgroup: ZC, fewer when that leaves
+// the device with too few workgroups (small volumes), never below 4; then
+// the same number of runs, of balanced lengths (a workgroup's time is its
+// run plus bz - 1 planes: 256x256x124 at b = 7 takes 30+30+30+28 instead of
+// 32+32+32+22).
+int f32_run_planes(const StatsLayout &L) {
+    const int64_t per_slab = (int64_t)((L.ox + TX - 1) / TX) * ((L.oy + TY - 1) / TY);
+    const int64_t slabs = (512 + per_slab - 1) / per_slab;
+    int zc = (int)((L.oz + slabs - 1) / slabs);
+    zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
+    const int runs = (L.oz + zc - 1) / zc;
+    return (L.oz + runs - 1) / runs;
+}
+}  // namespace
+
 hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
                         const int32_t block[3], bool pairs, void *workspace, hipStream_t stream) {
     StatsLayout L = stats_layout(dtype, dims, block, pairs);
@@ -373,17 +431,7 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
         }
         return hipGetLastError();
     }
-    // origin planes per workgroup: ZC, fewer when that leaves the device with
-    // too few workgroups (small volumes), never below 4
-    const int64_t per_slab = (int64_t)((L.ox + TX - 1) / TX) * ((L.oy + TY - 1) / TY);
-    const int64_t slabs = (512 + per_slab - 1) / per_slab;
-    int zc = (int)((L.oz + slabs - 1) / slabs);
-    zc = zc < 4 ? 4 : (zc > ZC ? ZC : zc);
-    // the same number of runs, of balanced lengths: a workgroup's time is
-    // its run plus bz - 1 planes (256x256x124 at b = 7: 30+30+30+28 instead
-    // of 32+32+32+22)
-    const int runs = (L.oz + zc - 1) / zc;
-    zc = (L.oz + runs - 1) / runs;
+    const int zc = f32_run_planes(L);
     dim3 grid((L.ox + TX - 1) / TX, (L.oy + TY - 1) / TY, (L.oz + zc - 1) / zc);
     hipLaunchKernelGGL(k_stats_f32, grid, dim3(256), (size_t)bz * 256 * 16, stream,
                        static_cast<const float *>(flt), dims[0], dims[1], dims[2], bx, by, bz,
@@ -443,6 +491,36 @@ hipError_t launch_stats(const void *flt, nrr_dtype dtype, const int32_t dims[3],
                         void *workspace, hipStream_t stream) {
     const int32_t b3[3] = {block, block, block};
     return launch_stats(flt, dtype, dims, b3, true, workspace, stream);
+}
+
+hipError_t launch_stats_f32_multi(const float *flt, const int32_t dims[3], const int32_t *blocks,
+                                  void *const *outs, int n, hipStream_t stream) {
+    if (n < 1 || n > kStatsJobs) return hipErrorInvalidValue;
+    StatsF32Jobs J{};
+    J.n = n;
+    int gx = 0, gy = 0, gz = 0, maxb = 0;
+    for (int i = 0; i < n; ++i) {
+        if (blocks[i] < 1 || blocks[i] > MAXB) return hipErrorInvalidValue;
+        const int32_t b3[3] = {blocks[i], blocks[i], blocks[i]};
+        const StatsLayout L = stats_layout(NRR_F32, dims, b3, false);
+        StatsF32Job &j = J.job[i];
+        j.b = blocks[i];
+        j.ox = L.ox;
+        j.oy = L.oy;
+        j.oz = L.oz;
+        j.zc = f32_run_planes(L);
+        j.tiles_x = (L.ox + TX - 1) / TX;
+        j.tiles_y = (L.oy + TY - 1) / TY;
+        j.z_first = gz;
+        gz += (L.oz + j.zc - 1) / j.zc;
+        j.out = static_cast<StatF32 *>(outs[i]);
+        gx = std::max(gx, j.tiles_x);
+        gy = std::max(gy, j.tiles_y);
+        maxb = std::max(maxb, (int)blocks[i]);
+    }
+    hipLaunchKernelGGL(k_stats_f32_multi, dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(256),
+                       (size_t)maxb * 256 * 16, stream, flt, dims[0], dims[1], dims[2], J);
+    return hipGetLastError();
 }
 
 }  // namespace nrr

@@ -185,4 +185,12 @@ hipError_t launch_select_stats(const uint64_t *keys, int64_t n, const BoxGrid &G
                                const uint16_t *flt, const int32_t dims[3], int32_t block,
                                const StatsLayout &L, void *stats, hipStream_t stream);
 
+// Float window statistics of n (1..kStatsJobs) cubic block edges over one
+// volume in one launch (stats.hip), edge blocks[i]'s records into outs[i]
+// (each laid out as launch_stats lays out that edge's workspace).  Several
+// short, latency-bound statistics passes then share the device.
+constexpr int kStatsJobs = 4;
+hipError_t launch_stats_f32_multi(const float *flt, const int32_t dims[3], const int32_t *blocks,
+                                  void *const *outs, int n, hipStream_t stream);
+
 }  // namespace nrr
