@@ -464,6 +464,26 @@ struct ForkSet {
 std::mutex g_fork_mu;
 ForkSet g_fork[64];
 
+// The current device's fork set, created on first use (call with g_fork_mu
+// held: the caller's record/wait sequence then owns the events).
+hipError_t fork_set(ForkSet **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    ForkSet &fs = g_fork[dev];
+    if (!fs.side) {
+        e = hipStreamCreateWithFlags(&fs.side, hipStreamNonBlocking);  // default priority
+        // the events order work of this device only: no system-scope fences
+        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.fork, fl);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.join, fl);
+        if (e != hipSuccess) return e;
+    }
+    *out = &fs;
+    return hipSuccess;
+}
+
 }  // namespace
 
 nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dtype dtype,
@@ -531,15 +551,10 @@ nrr_status nrr_select_and_window_stats(const void *ref, const void *flt, nrr_dty
     if (e != hipSuccess) return hip_status(e, "device query");
     if (dev < 0 || dev >= 64) return fail(NRR_ERR_UNSUPPORTED, "device index %d (0..63 built)", dev);
     std::lock_guard<std::mutex> lk(g_fork_mu);
-    ForkSet &fs = g_fork[dev];
-    if (!fs.side) {
-        e = hipStreamCreateWithFlags(&fs.side, hipStreamNonBlocking);  // default priority
-        // the events order work of this device only: no system-scope fences
-        const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.fork, fl);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&fs.join, fl);
-        if (e != hipSuccess) return hip_status(e, "second stream creation");
-    }
+    ForkSet *fsp = nullptr;
+    e = fork_set(&fsp);
+    if (e != hipSuccess) return hip_status(e, "second stream creation");
+    ForkSet &fs = *fsp;
     // keys on `stream`; then the statistics on the second stream (forked
     // here, so the selection's one-workgroup kernel, next on `stream`, is
     // placed before the statistics fill the device); `stream` joins them
@@ -1006,27 +1021,41 @@ struct nrr_batch_plan {
 
 namespace {
 
-// The launches of one batch on `st`: window statistics per block size, the
-// batched selection, the persistent search.
-hipError_t batch_enqueue(const nrr_batch_plan &P, hipStream_t st) {
+// The window statistics of every block size of a batch on `st`.
+hipError_t batch_stats(const nrr_batch_plan &P, hipStream_t st) {
     const size_t nb = P.L.bvals.size();
     if (P.dtype == NRR_F32 && nb >= 1 && nb <= (size_t)nrr::kStatsJobs) {
         void *outs[nrr::kStatsJobs];
         for (size_t i = 0; i < nb; ++i) outs[i] = P.ws + P.L.stats_off[i];
-        hipError_t e = nrr::launch_stats_f32_multi(static_cast<const float *>(P.flt), P.dims,
-                                                   P.L.bvals.data(), outs, (int)nb, st);
-        if (e != hipSuccess) return e;
-    } else {
-        for (size_t i = 0; i < nb; ++i) {
-            hipError_t e = nrr::launch_stats(P.flt, P.dtype, P.dims, P.L.bvals[i],
-                                             P.ws + P.L.stats_off[i], st);
-            if (e != hipSuccess) return e;
-        }
+        return nrr::launch_stats_f32_multi(static_cast<const float *>(P.flt), P.dims,
+                                           P.L.bvals.data(), outs, (int)nb, st);
     }
-    if (P.nsets == 0) return hipSuccess;
-    hipError_t e = nrr::launch_select_batch(
-        P.ref, P.dtype, P.dims, reinterpret_cast<const nrr::BatchSelectSet *>(P.ws + P.L.sel_off),
-        P.nsets, P.L.max_cand, st);
+    for (size_t i = 0; i < nb; ++i) {
+        hipError_t e = nrr::launch_stats(P.flt, P.dtype, P.dims, P.L.bvals[i],
+                                         P.ws + P.L.stats_off[i], st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// The launches of one batch on `st`: the window statistics (read `flt`) on the
+// library's second stream, beside the batched selection (reads `ref`) on
+// `st`; `st` joins them before the persistent search.
+hipError_t batch_enqueue(const nrr_batch_plan &P, hipStream_t st) {
+    if (P.nsets == 0) return batch_stats(P, st);
+    std::lock_guard<std::mutex> lk(g_fork_mu);
+    ForkSet *fs = nullptr;
+    hipError_t e = fork_set(&fs);
+    if (e == hipSuccess) e = hipEventRecord(fs->fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(fs->side, fs->fork, 0);
+    if (e == hipSuccess) e = batch_stats(P, fs->side);
+    if (e == hipSuccess) e = hipEventRecord(fs->join, fs->side);
+    if (e == hipSuccess)
+        e = nrr::launch_select_batch(
+            P.ref, P.dtype, P.dims,
+            reinterpret_cast<const nrr::BatchSelectSet *>(P.ws + P.L.sel_off), P.nsets,
+            P.L.max_cand, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, fs->join, 0);
     if (e != hipSuccess) return e;
     return nrr::launch_match_batch(P.dtype,
                                    reinterpret_cast<const nrr::BatchSet *>(P.ws + P.L.sets_off),
@@ -1138,8 +1167,13 @@ nrr_status nrr_batch_plan_create(const void *ref, const void *flt, nrr_dtype dty
                           hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && use_graph) {
+        {  // the second stream exists before the capture begins
+            std::lock_guard<std::mutex> lk(g_fork_mu);
+            ForkSet *fs = nullptr;
+            e = fork_set(&fs);
+        }
         hipStream_t cs = nullptr;
-        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
         if (e == hipSuccess) {
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
