@@ -432,7 +432,12 @@ nrr_status nrr_set_tuned_shape(nrr_dtype dtype, int32_t block, int32_t window,
  * *plan receives a host object released by nrr_batch_plan_destroy.
  *
  * nrr_batch_plan_run enqueues one batch on `stream` (asynchronous; a graph
- * launch when the plan holds one).  Runs of one plan must not overlap. */
+ * launch when the plan holds one).  Runs of one plan must not overlap.  The
+ * window statistics run on this library's second stream (the one
+ * nrr_select_and_window_stats uses), forked from `stream` beside the
+ * selection and joined back before the search, in eager runs and in the
+ * captured graph alike; the same caveats hold (enqueues on one device are
+ * serialised; a capture on another host thread at the same time fails). */
 typedef struct {
     int32_t block, window, stride;
     double fraction;
