@@ -347,11 +347,14 @@ struct ThrShared {
     uint32_t s_left, s_count;
 };
 
-// The select of one 1024-thread workgroup (see above).
+// The select of one 1024-thread workgroup (see above), for at most NK * 1024
+// keys (NK key slots per thread).
+template <int NK = kThrKeys>
 __device__ __attribute__((always_inline)) inline void select_threshold_wg(
     const uint64_t *__restrict__ keys, int64_t n, int64_t k, const int64_t *__restrict__ kd,
     SelectState *__restrict__ st, const BoxGrid &G, int32_t *__restrict__ centers,
     ThrShared &sm) {
+    static_assert(NK % 4 == 0 && NK <= kThrKeys, "whole scan entries, within the LDS tables");
     uint32_t *hist_c = sm.hist_c, *hist = sm.hist, *pre = sm.pre;
     uint64_t *list = sm.list;
     uint64_t &s_prefix = sm.s_prefix, &s_mask = sm.s_mask, &s_or = sm.s_or;
@@ -366,16 +369,16 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
         s_or = 0;
         s_count = 0;
     }
-    uint64_t kr[kThrKeys];  // all loads issued before any is used
+    uint64_t kr[NK];  // all loads issued before any is used
 #pragma unroll
-    for (int j = 0; j < kThrKeys; ++j) {
+    for (int j = 0; j < NK; ++j) {
         const int64_t i = (int64_t)j * 1024 + tid;
         kr[j] = i < n ? keys[i] : 0;
     }
     __syncthreads();
     uint64_t orv = 0;
 #pragma unroll
-    for (int j = 0; j < kThrKeys; ++j) orv |= kr[j];
+    for (int j = 0; j < NK; ++j) orv |= kr[j];
     for (int off = 32; off > 0; off >>= 1) orv |= __shfl_xor(orv, off);
     if (lane == 0) atomicOr((unsigned long long *)&s_or, (unsigned long long)orv);
     __syncthreads();
@@ -389,7 +392,7 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
             for (int i = tid; i < 256 * kThrCopies; i += 1024) hist_c[i] = 0;
             __syncthreads();
 #pragma unroll
-            for (int j = 0; j < kThrKeys; ++j)
+            for (int j = 0; j < NK; ++j)
                 if ((int64_t)j * 1024 + tid < n && (kr[j] & mask) == prefix)
                     atomicAdd(&hrow[((kr[j] >> shift) & 0xff) * kThrCopies], 1u);
             __syncthreads();
@@ -452,7 +455,7 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
             const uint64_t p2 = s_prefix, m2 = s_mask;
             uint32_t mm = 0, wave_total = 0;
 #pragma unroll
-            for (int j = 0; j < kThrKeys; ++j) {
+            for (int j = 0; j < NK; ++j) {
                 const bool m = (int64_t)j * 1024 + tid < n && (kr[j] & m2) == p2;
                 mm |= (uint32_t)m << j;
                 wave_total += (uint32_t)__popcll(__ballot(m));
@@ -461,7 +464,7 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
             if (lane == 0 && wave_total) base = atomicAdd(&s_count, wave_total);
             base = __shfl(base, 0);
 #pragma unroll
-            for (int j = 0; j < kThrKeys; ++j) {
+            for (int j = 0; j < NK; ++j) {
                 const bool m = (mm >> j) & 1;
                 const uint64_t b = __ballot(m);
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi(
@@ -484,7 +487,7 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
     const int64_t take = s_need;  // equal keys kept, lowest indices first
     uint32_t fgt = 0, feq = 0;  // bit j: key j of this thread is above / equal to the K-th
 #pragma unroll
-    for (int j = 0; j < kThrKeys; ++j) {
+    for (int j = 0; j < NK; ++j) {
         const bool in = (int64_t)j * 1024 + tid < n;
         const bool gt = in && kr[j] > kth, eq = in && kr[j] == kth;
         fgt |= (uint32_t)gt << j;
@@ -494,8 +497,8 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
         if (lane == 0) pre[j * 16 + w] = a | e << 16;  // each < 2^16 (n <= 2^15)
     }
     __syncthreads();
-    if (tid < 64) {  // exclusive scan of the 16 kThrKeys entries, 8 per lane
-        constexpr int PL = kThrKeys * 16 / 64;
+    if (tid < 64) {  // exclusive scan of the NK * 16 entries, NK / 4 per lane
+        constexpr int PL = NK * 16 / 64;
         uint32_t v[PL], sum = 0;
 #pragma unroll
         for (int i = 0; i < PL; ++i) {
@@ -1256,7 +1259,8 @@ __global__ __launch_bounds__(64) void k_batch_keys_f32(const float *__restrict__
 }
 
 // Per set, the plain path's one-workgroup select (radix passes for the K-th
-// key, then the ordered compaction), so a set's centres are a plain call's.
+// key, then the ordered compaction), so a set's centres are a plain call's;
+// key slots for the batched grids only (at most kBatchCand candidates).
 __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__restrict__ sets) {
     __shared__ ThrShared sm;
     const BatchSelectSet &S = sets[blockIdx.x];
@@ -1268,7 +1272,8 @@ __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__r
     G.g[0] = S.gx;
     G.g[1] = S.gy;
     G.g[2] = S.gz;
-    select_threshold_wg(S.keys, S.ncand, S.k, nullptr, nullptr, G, S.centers, sm);
+    select_threshold_wg<kBatchCand / 1024>(S.keys, S.ncand, S.k, nullptr, nullptr, G, S.centers,
+                                           sm);
 }
 
 }  // namespace
@@ -1276,6 +1281,7 @@ __global__ __launch_bounds__(1024) void k_select_batch(const BatchSelectSet *__r
 hipError_t launch_select_batch(const void *vol, nrr_dtype dtype, const int32_t dims[3],
                                const BatchSelectSet *sets, int nsets, int64_t max_cand,
                                hipStream_t stream) {
+    static_assert(kBatchCand % 4096 == 0, "whole select scan entries per set");
     if (max_cand > 0 && dtype == NRR_U16)
         hipLaunchKernelGGL(k_batch_keys_u16, dim3((unsigned)((max_cand + 3) / 4), (unsigned)nsets),
                            dim3(256), 0, stream, static_cast<const uint16_t *>(vol), dims[0],
