@@ -100,10 +100,13 @@ def test_float_select_one_workgroup(torch_dev):
 
 
 @pytest.mark.parametrize("dims,b,stride,wide", [
-    ((40, 33, 21), 3, 1, False),   # 27 voxels: one partial load batch
-    ((31, 29, 23), 5, 2, True),    # 125: full batches and a partial one
-    ((40, 36, 30), 9, 3, True),    # 729: many batches
+    ((40, 33, 21), 3, 1, False),   # 27 voxels: nine rows of three
+    ((31, 29, 23), 5, 2, True),    # 125: 25 rows, a ring of four row buffers
+    ((40, 36, 30), 9, 3, True),    # 729: 81 rows
     ((17, 17, 16), 15, 1, True),   # 3375: the largest edge
+    ((30, 28, 26), 7, 2, True),    # the other row lengths of the row walk
+    ((33, 31, 29), 11, 3, True),
+    ((27, 26, 25), 13, 2, False),
 ])
 def test_float_keys_bitwise_against_the_oracle(torch_dev, dims, b, stride, wide):
     """Every candidate's float key (the FP64 two-pass variance summed in z, y,
