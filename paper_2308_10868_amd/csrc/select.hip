@@ -334,6 +334,7 @@ __device__ inline void hist_add(uint32_t *hist, uint32_t d, bool valid) {
 constexpr int kThrKeys = (int)(kRadixMultiMin / 1024);  // keys per thread
 static_assert(kRadixMultiMin % 1024 == 0, "whole keys per thread");
 constexpr int kThrCopies = 16;  // histogram copies (lane mod 16)
+constexpr int64_t kSmallSelect = 4096;  // grids up to this size take 4 key slots per thread
 
 // The select's LDS (a struct, so a fused kernel can overlay it with its other
 // work's LDS).
@@ -550,13 +551,15 @@ __device__ __attribute__((always_inline)) inline void select_threshold_wg(
     }
 }
 
+// NK key slots per thread: grids of at most NK * 1024 candidates.
+template <int NK>
 __global__ __launch_bounds__(1024) void k_select_threshold(const uint64_t *__restrict__ keys,
                                                            int64_t n, int64_t k,
                                                            const int64_t *__restrict__ kd,
                                                            SelectState *__restrict__ st, BoxGrid G,
                                                            int32_t *__restrict__ centers) {
     __shared__ ThrShared sm;
-    select_threshold_wg(keys, n, k, kd, st, G, centers, sm);
+    select_threshold_wg<NK>(keys, n, k, kd, st, G, centers, sm);
 }
 
 // The select and the 12-bit column statistics of a cubic block edge B in one
@@ -1447,9 +1450,12 @@ void select_from_keys(const uint64_t *keys, int64_t n, const BoxGrid &G, int64_t
                            n, st, tiles);
         hipLaunchKernelGGL(k_compact, dim3((unsigned)L.n_tiles), dim3(256), 0, stream, keys, n,
                            st, tiles, G, k, kd, centers);
+    } else if (n <= kSmallSelect) {  // one workgroup, few key slots (less work per pass)
+        hipLaunchKernelGGL(k_select_threshold<kSmallSelect / 1024>, dim3(1), dim3(1024), 0, stream,
+                           keys, n, k, kd, st, G, centers);
     } else {  // one workgroup: the K-th key and the compaction
-        hipLaunchKernelGGL(k_select_threshold, dim3(1), dim3(1024), 0, stream, keys, n, k, kd, st,
-                           G, centers);
+        hipLaunchKernelGGL(k_select_threshold<kThrKeys>, dim3(1), dim3(1024), 0, stream, keys, n,
+                           k, kd, st, G, centers);
     }
 }
 

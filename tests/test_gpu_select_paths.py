@@ -99,6 +99,22 @@ def test_float_select_one_workgroup(torch_dev):
     assert np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+@pytest.mark.parametrize("dims,frac", [((18, 18, 18), 0.37), ((19, 18, 18), 0.37),
+                                       ((18, 18, 18), 1.0)])
+def test_select_around_the_small_grid_bound(torch_dev, dtype, dims, frac):
+    """Grids of 4096 candidates take the select with 4 key slots per thread,
+    4352 candidates the one with 32: both against the oracle, with plateaus of
+    equal keys around the K-th."""
+    say("select around 4096 candidates", dtype, dims, frac)
+    rng = np.random.default_rng(sum(dims))
+    vol = rng.integers(0, 6, size=dims[::-1]) * 500
+    vol = vol.astype(np.uint16) if dtype == "u16" else vol.astype(np.float32) * 0.37
+    got = gpu_select(vol, 3, 1, frac)
+    exp, _ = oracle.select(vol, 3, 1, frac)
+    assert np.array_equal(got, exp)
+
+
 @pytest.mark.parametrize("dims,b,stride,wide", [
     ((40, 33, 21), 3, 1, False),   # 27 voxels: nine rows of three
     ((31, 29, 23), 5, 2, True),    # 125: 25 rows, a ring of four row buffers
